@@ -1,0 +1,153 @@
+"""Seeded synthetic inputs for partial-circulant LASSO recovery.
+
+This module only draws random numbers and rounds them to float32.  It holds
+none of the method's arithmetic: no products with the sensing matrix, no FFT,
+no thresholds.  Both the FP64 oracle (tests) and the HIP path (tests, bench)
+take their inputs from here, so neither needs the other to build a workload.
+
+Workload shapes follow the paper's synthetic experiments (Section 6: Gaussian
+nonzeros at random positions, a Gaussian circulant generator) at the sizes of
+the five configurations below:
+
+  cfg1  n=4096,  d=4,  k=40         parity case
+  cfg2  n=2^22,  d=4,  k=2^14       large single signal
+  cfg3  4096x4096 scene, 20000 lognormal point sources, +-1 2-D sensing
+        kernel, sigma=2 Gaussian PSF truncated to 15x15, 2x decimation per axis
+  cfg4  512 signals, n_i = 2^e, e uniform in {12..18}, d=4, k_i=n_i/256
+  cfg5  shared generator, n=2^16, d=4, batch 64 signals with k=256
+
+Every draw is made in float64 and then rounded to float32 (the arrays handed to
+both sides are those float32 values).  The generator c has entries
+N(0, 1/m), i.e. standard deviation m^{-1/2}.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+SEED_BASE = 17070224
+
+
+def _f32(a):
+    return np.asarray(a, dtype=np.float64).astype(np.float32)
+
+
+@dataclasses.dataclass
+class Signal1D:
+    """One 1-D draw: circulant generator c (first column), sparse truth x*."""
+    n: int
+    d: int
+    k: int
+    c: np.ndarray        # float32, length n
+    x_true: np.ndarray   # float32, length n, k nonzeros
+    support: np.ndarray  # int64, sorted positions of the nonzeros
+
+    @property
+    def m(self) -> int:
+        return self.n // self.d
+
+
+def draw_1d(rng: np.random.Generator, n: int, d: int, k: int) -> Signal1D:
+    """Draw c ~ N(0,1/m) (length n), then a support of k distinct positions,
+    then k N(0,1) values.  This draw order is fixed."""
+    m = n // d
+    c = rng.standard_normal(n) / np.sqrt(m)
+    supp = rng.choice(n, k, replace=False)
+    vals = rng.standard_normal(k)
+    x = np.zeros(n)
+    x[supp] = vals
+    return Signal1D(n=n, d=d, k=k, c=_f32(c), x_true=_f32(x),
+                    support=np.sort(supp.astype(np.int64)))
+
+
+def signal(n: int, d: int, k: int, seed: int) -> Signal1D:
+    """A 1-D draw of arbitrary size (test cases)."""
+    return draw_1d(np.random.default_rng(seed), n, d, k)
+
+
+def cfg1(seed_offset: int = 0) -> Signal1D:
+    return draw_1d(np.random.default_rng(SEED_BASE + 1 + seed_offset), 4096, 4, 40)
+
+
+def cfg2(seed_offset: int = 0) -> Signal1D:
+    return draw_1d(np.random.default_rng(SEED_BASE + 2 + seed_offset), 1 << 22, 4, 1 << 14)
+
+
+CFG1_PARAMS = dict(ista_iters=500, admm_iters=200, rho=1.0, lam_frac=0.01)
+CFG2_PARAMS = dict(ista_iters=300, admm_iters=100, rho=1.0, lam_frac=0.01)
+
+
+@dataclasses.dataclass
+class Scene2D:
+    """2-D draw: sensing kernel s (+-1, full grid), PSF h (wrapped, sum 1),
+    sparse scene x*."""
+    n1: int
+    n2: int
+    d1: int
+    d2: int
+    s: np.ndarray        # float32 (n1, n2)
+    h: np.ndarray        # float32 (n1, n2), wrapped PSF
+    x_true: np.ndarray   # float32 (n1, n2)
+
+
+def gaussian_psf(n1: int, n2: int, sigma: float = 2.0, half: int = 7) -> np.ndarray:
+    """exp(-(a^2+b^2)/(2 sigma^2)) for a,b in [-half, half], normalised to sum
+    one, placed periodically at (a mod n1, b mod n2)."""
+    a = np.arange(-half, half + 1)
+    g = np.exp(-(a[:, None] ** 2 + a[None, :] ** 2) / (2.0 * sigma * sigma))
+    g /= g.sum()
+    h = np.zeros((n1, n2))
+    for i, ai in enumerate(a):
+        for j, bj in enumerate(a):
+            h[ai % n1, bj % n2] += g[i, j]
+    return h
+
+
+def draw_2d(rng: np.random.Generator, n1: int, n2: int, n_src: int,
+            sigma: float = 2.0, half: int = 7) -> Scene2D:
+    """Draw order: source positions, lognormal(0,1) amplitudes, +-1 kernel."""
+    pos = rng.choice(n1 * n2, n_src, replace=False)
+    amp = rng.lognormal(0.0, 1.0, n_src)
+    s = rng.choice(np.array([-1.0, 1.0]), (n1, n2))
+    x = np.zeros(n1 * n2)
+    x[pos] = amp
+    h = gaussian_psf(n1, n2, sigma, half)
+    return Scene2D(n1=n1, n2=n2, d1=2, d2=2, s=_f32(s), h=_f32(h),
+                   x_true=_f32(x.reshape(n1, n2)))
+
+
+def cfg3(seed_offset: int = 0) -> Scene2D:
+    return draw_2d(np.random.default_rng(SEED_BASE + 3 + seed_offset), 4096, 4096, 20000)
+
+
+CFG3_PARAMS = dict(admm_iters=200, rho=1.0, lam_frac=0.005)
+
+
+def cfg4(seed_offset: int = 0, count: int = 512, e_lo: int = 12, e_hi: int = 18):
+    """Batched uneven sizes: all exponents first, then each signal's draws in
+    the 1-D order (c, support, values); k_i = n_i/256."""
+    rng = np.random.default_rng(SEED_BASE + 4 + seed_offset)
+    e = rng.integers(e_lo, e_hi + 1, size=count)
+    out = []
+    for ei in e:
+        n = 1 << int(ei)
+        out.append(draw_1d(rng, n, 4, n // 256))
+    return out
+
+
+CFG4_PARAMS = dict(ista_iters=200, lam_frac=0.01)
+
+
+def cfg5(seed_offset: int = 0, n: int = 1 << 16, d: int = 4, batch: int = 64, k: int = 256):
+    """Shared generator c, then `batch` sparse truths (support, values)."""
+    rng = np.random.default_rng(SEED_BASE + 5 + seed_offset)
+    m = n // d
+    c = _f32(rng.standard_normal(n) / np.sqrt(m))
+    xs = np.zeros((batch, n))
+    for b in range(batch):
+        supp = rng.choice(n, k, replace=False)
+        xs[b, supp] = rng.standard_normal(k)
+    return c, _f32(xs)
+
+
+CFG5_PARAMS = dict(K=50, every=10, lam_frac=0.01)
