@@ -1,0 +1,177 @@
+"""Benchmark: ISTA and ADMM LASSO recovery with A = P C at n = 2^22 on one GPU.
+
+One step = one ISTA solve (300 iterations) + one ADMM solve (rho = 1, 100
+iterations) on the large single-signal workload: n = 2^22, m = 2^20 (d = 4),
+c ~ N(0, 1/m) stored as n floats, x* with 2^14 N(0,1) nonzeros, y = A x*,
+lam = 0.01 ||A^T y||_inf, tau = 1/max|c_hat|^2.  Inputs are seeded synthetic
+draws, resident in HBM before the timed region; y, tau and lam are computed
+with the library's own operators.  value = (300 + 100) iterations per step /
+seconds per step.
+
+Printed: one JSON line with the metric, the per-solver rates, the roofline of
+the dominant kernel (its algorithmic bytes per launch over its average launch
+duration, both measured here with HIP events on the launching stream) and the
+FP64 oracle timed on this host's cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_bytes(n, d):
+    """Algorithmic HBM bytes per launch of each per-iteration kernel (float32).
+
+    passA (ISTA and ADMM): spectrum Y read + write (2 * 4n), c_hat table read
+    (N + 1 complex = 4n), y_hat read for the m/2 + 1 alias classes (4m).
+    passB_ista: Y read + write and the iterate x read + write (16n).
+    passB_admm: Y read + write and the dual u read + write (16n).
+    """
+    m = n // d
+    a = 12 * n + 4 * m
+    return {"passA_ista": a, "passB_ista": 16 * n, "passA_admm": a, "passB_admm": 16 * n}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the solver path is single-GPU "
+              "(multi-GPU sharding is a design note, not an implemented path).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1707_02244_amd as cs
+    import workloads
+
+    dev = torch.device("cuda:0")
+    sig = workloads.cfg2()
+    prm = workloads.CFG2_PARAMS
+    n, d = sig.n, sig.d
+    c = torch.from_numpy(sig.c).to(dev)
+    xs = torch.from_numpy(sig.x_true).to(dev)
+    y = cs.circ_apply(c, d, xs)
+    tau = float(1.0 / cs.circ_norm_bound(c).item())
+    lam = float(prm["lam_frac"] * cs.circ_apply_T(c, d, y).abs().max().item())
+    rho = prm["rho"]
+    T_ista, T_admm = prm["ista_iters"], prm["admm_iters"]
+    x = torch.empty(n, device=dev)
+    xa, za, ua = (torch.empty(n, device=dev) for _ in range(3))
+    torch.cuda.synchronize()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        cs.ista_solve(c, d, y, lam, tau, T_ista, x=x)
+        if ev is not None:
+            ev[1].record()
+        cs.admm_solve(c, d, y, lam, rho, T_admm, x=xa, z=za, u=ua)
+        if ev is not None:
+            ev[2].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ista_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    admm_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    ms_per_step = wall * 1e3 / args.steps
+    value = (T_ista + T_admm) / (ms_per_step / 1e3)
+
+    out = {
+        "metric": "ISTA/ADMM iterations/s at n=2^22 (plain solver, 1 GPU)",
+        "value": value,
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "large single signal: n=2^22, m=2^20 (d=4), k=2^14; "
+                               "ISTA 300 it + ADMM(rho=1) 100 it per step",
+                   "n": n, "d": d, "ista_iters": T_ista, "admm_iters": T_admm},
+        "ista_it_s": T_ista / (ista_ms / 1e3),
+        "admm_it_s": T_admm / (admm_ms / 1e3),
+        "ista_ms_per_solve": ista_ms,
+        "admm_ms_per_solve": admm_ms,
+    }
+
+    # model GB/s for the whole iteration (per-kernel bytes summed)
+    kb = kernel_bytes(n, d)
+    out["ista_model_GBs"] = (kb["passA_ista"] + kb["passB_ista"]) * out["ista_it_s"] / 1e9
+    out["admm_model_GBs"] = (kb["passA_admm"] + kb["passB_admm"]) * out["admm_it_s"] / 1e9
+
+    if not args.no_roofline:
+        cs.timing_enable(True)
+        step()
+        torch.cuda.synchronize()
+        cs.timing_enable(False)
+        kern = {}
+        for name in kb:
+            cnt, tot = cs.timing_read(name)
+            kern[name] = {"launches": cnt, "avg_us": 1e3 * tot / max(cnt, 1), "total_ms": tot,
+                          "bytes_per_launch": kb[name],
+                          "GBs": kb[name] / (tot / max(cnt, 1) / 1e3) / 1e9 if cnt else None}
+        dom = max(kern, key=lambda k: kern[k]["total_ms"])
+        ach = kern[dom]["GBs"]
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                           "avg_launch_us": kern[dom]["avg_us"],
+                           "bytes_per_launch": kern[dom]["bytes_per_launch"]}
+        out["kernels"] = kern
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sig, prm, tau, lam)
+    print(json.dumps(out))
+
+
+def cpu_baseline(sig, prm, tau, lam):
+    """The FP64 oracle (FFT reference) on a bounded sample of the same workload:
+    a few ISTA and ADMM iterations at n = 2^22, scaled to the step's 300:100
+    iteration mix.  numpy's FFT runs one 1-D transform on one thread."""
+    from oracle import fftref
+    op = fftref.Operator(sig.c.astype(np.float64), sig.d)
+    y = op.A(sig.x_true.astype(np.float64)).astype(np.float32).astype(np.float64)
+    ki, ka = 8, 4
+    t0 = time.perf_counter()
+    fftref.ista(op, y, lam, tau, ki)
+    ti = (time.perf_counter() - t0) / ki
+    t0 = time.perf_counter()
+    fftref.admm(op, y, lam, prm["rho"], ka)
+    ta = (time.perf_counter() - t0) / ka
+    T_i, T_a = prm["ista_iters"], prm["admm_iters"]
+    return {"value": (T_i + T_a) / (T_i * ti + T_a * ta), "unit": "iterations/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "FP64 FFT reference at n=2^22: %d ISTA + %d ADMM iterations "
+                      "(%.3f s and %.3f s per iteration), rate for the 300:100 mix; "
+                      "host has %d usable cores" % (ki, ka, ti, ta, len(os.sched_getaffinity(0)))}
+
+
+if __name__ == "__main__":
+    main()

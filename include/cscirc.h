@@ -1,0 +1,109 @@
+/*
+ * cscirc.h -- C ABI of the MI355X (gfx950) partial-circulant LASSO library.
+ *
+ * Problem (Fiandrotti, Fosson, Ravazzi, Magli, arXiv 1707.02244):
+ *   measurements y = A x* with A = P C (Eq. 1; Section 4.3), where
+ *     C (n x n) is circulant with first column c:  C[i][j] = c[(i - j) mod n]
+ *     P (m x n) keeps rows 0, d, 2d, ..., (m-1)d:   A[r][j] = c[(r*d - j) mod n]
+ *   and recovery solves the LASSO (Eq. 3, halved)
+ *     min_x 1/2 ||y - A x||^2 + lambda ||x||_1
+ *   with ISTA (Alg. 1) or ADMM (Alg. 2).
+ *
+ * Conventions for every call:
+ *   - Every float pointer is a DEVICE pointer on the current HIP device,
+ *     float32, densely packed, owned by the caller.  The library never frees
+ *     or retains it beyond the work it enqueues.
+ *   - n is a power of two with 256 <= n <= 2^25; d is 2, 4, 8 or 16; m = n/d.
+ *   - All work is enqueued on `stream` (a hipStream_t; 0 is the null stream)
+ *     and the call returns without synchronising.  Outputs are valid once the
+ *     stream has been synchronised.
+ *   - Arguments are validated on the host before anything is enqueued; a bad
+ *     argument returns CS_EINVAL and enqueues nothing.  cs_last_error() gives
+ *     a message (per thread).
+ *   - The first call for a given (device, n, d) builds a plan: twiddle tables
+ *     (double precision on the host) and a workspace of about 3*n*4 bytes,
+ *     allocated with hipMalloc and kept until the process ends.  Calls that
+ *     share a plan share its workspace: issue them on one stream (or
+ *     serialise them); concurrent calls with the same (n, d) on different
+ *     streams race.
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef CSCIRC_H
+#define CSCIRC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CS_OK = 0,
+  CS_EINVAL = -1,   /* invalid argument (checked before any work is enqueued) */
+  CS_ENOMEM = -2,   /* device allocation for a plan failed                    */
+  CS_EHIP = -3,     /* a HIP runtime call or kernel launch reported an error  */
+  CS_ENOTSUP = -4   /* a valid but unsupported request                        */
+} cs_status;
+
+typedef struct ihipStream_t* cs_stream; /* hipStream_t */
+
+/* y = A x = P C x  (Eq. 1).  c: n, x: n, y: m.  */
+cs_status cs_circ_apply(const float* c, int64_t n, int32_t d, const float* x, float* y,
+                        cs_stream stream);
+
+/* x = A^T r = C^T P^T r  (the transpose product of Alg. 1, step 4).
+ * c: n, r: m, x: n.  */
+cs_status cs_circ_apply_T(const float* c, int64_t n, int32_t d, const float* r, float* x,
+                          cs_stream stream);
+
+/* max_k |c_hat_k|^2 over the n-point DFT of c, written to out[0] (device).
+ * It bounds ||A||_2^2 from above, so tau = 1/out is an admissible ISTA step
+ * (Alg. 1 asks for tau in (0, ||A||_2^-2)).  */
+cs_status cs_circ_norm_bound(const float* c, int64_t n, float* out, cs_stream stream);
+
+/* ISTA, Alg. 1:  x(0) = 0;  for t = 1..iters:
+ *     x(t) = eta_{tau*lambda}( x(t-1) + tau A^T (y - A x(t-1)) )
+ * eta is the soft threshold of Eq. 4 (strict comparison).  The threshold is
+ * tau*lambda (proximal-gradient reading of the LASSO of Eq. 3 with alpha =
+ * lambda).  y: m.  x: n, output x(iters) (zero when iters == 0).
+ * Requires lambda >= 0, tau > 0, iters >= 0.  obj must be NULL.  */
+cs_status cs_ista_solve(const float* c, int64_t n, int32_t d, const float* y, float lambda,
+                        float tau, int32_t iters, float* x, float* obj, cs_stream stream);
+
+/* ADMM, Alg. 2 (scaled dual u):  for t = 1..iters:
+ *     x(t) = (A^T A + rho I)^{-1} (A^T y + rho (z(t-1) - u(t-1)))
+ *     z(t) = eta_{lambda/rho}( x(t) + u(t-1) )
+ *     u(t) = u(t-1) + x(t) - z(t)
+ * The inverse is applied exactly through the Woodbury identity with the
+ * m x m circulant A A^T (never formed).  warm == 0: start from
+ * x = z = u = 0 (Alg. 2's initial guess); warm != 0: start from the z and u
+ * passed in.  x, z, u: n each, outputs x(iters), z(iters), u(iters); u is
+ * also used as the dual state during the solve.  With iters == 0 and warm ==
+ * 0 all three are zeroed; with warm != 0 they are left as passed.
+ * Requires lambda >= 0, rho > 0, iters >= 0.  obj must be NULL.  */
+cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, float lambda,
+                        float rho, int32_t iters, int32_t warm, float* x, float* z, float* u,
+                        float* obj, cs_stream stream);
+
+/* Kernel timing (diagnostics, for benchmarks).  While enabled, every launch
+ * of the solvers' two per-iteration kernels is bracketed by a pair of
+ * hipEvents recorded on the caller's stream.  cs_timing_read waits for the
+ * recorded launches of one kernel ("passA_ista", "passB_ista", "passA_admm",
+ * "passB_admm"), returns their count and summed duration in milliseconds,
+ * and forgets them.  Timing adds event records to the stream; leave it off
+ * for production runs.  */
+cs_status cs_timing_enable(int32_t on);
+cs_status cs_timing_read(const char* kernel, int64_t* launches, double* total_ms);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char* cs_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t cs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSCIRC_H */

@@ -1,0 +1,7 @@
+"""MI355X-native partial-circulant LASSO recovery (ISTA / ADMM with A = P C).
+
+The compute path is the HIP library libcscirc.so (C ABI in include/cscirc.h);
+this package only marshals torch tensors into it.
+"""
+from ._lib import (CsError, LIB_PATH, EXPORTS, load, circ_apply, circ_apply_T,  # noqa: F401
+                   circ_norm_bound, ista_solve, admm_solve, timing_enable, timing_read, version)

@@ -1,0 +1,157 @@
+"""ctypes binding of libcscirc.so: argument marshalling only.
+
+Every function takes torch tensors that already live on the GPU, checks dtype,
+device, contiguity and length, and passes raw device pointers plus the current
+HIP stream to the C ABI declared in include/cscirc.h.  All arithmetic runs in
+the library's HIP kernels; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcscirc.so")
+
+CS_OK, CS_EINVAL, CS_ENOMEM, CS_EHIP, CS_ENOTSUP = 0, -1, -2, -3, -4
+_NAMES = {CS_EINVAL: "CS_EINVAL", CS_ENOMEM: "CS_ENOMEM", CS_EHIP: "CS_EHIP", CS_ENOTSUP: "CS_ENOTSUP"}
+
+EXPORTS = ["cs_circ_apply", "cs_circ_apply_T", "cs_circ_norm_bound", "cs_ista_solve",
+           "cs_admm_solve", "cs_timing_enable", "cs_timing_read", "cs_last_error", "cs_version"]
+
+
+class CsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_NAMES.get(status, str(status)), msg))
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libcscirc.so is not built (%s); run __graft_entry__.build() "
+                          "or python paper_1707_02244_amd/build.py" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, F = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_float
+    sig = {
+        "cs_circ_apply": [P, I64, I32, P, P, P],
+        "cs_circ_apply_T": [P, I64, I32, P, P, P],
+        "cs_circ_norm_bound": [P, I64, P, P],
+        "cs_ista_solve": [P, I64, I32, P, F, F, I32, P, P, P],
+        "cs_admm_solve": [P, I64, I32, P, F, F, I32, I32, P, P, P, P, P],
+        "cs_timing_enable": [I32],
+        "cs_timing_read": [ctypes.c_char_p, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double)],
+        "cs_last_error": [],
+        "cs_version": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.cs_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(st):
+    if st != CS_OK:
+        raise CsError(st, load().cs_last_error().decode())
+
+
+def _ptr(t, name, numel=None):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if t.dtype != torch.float32:
+        raise TypeError("%s must be float32, got %s" % (name, t.dtype))
+    if not t.is_cuda:
+        raise ValueError("%s must be on the GPU" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def circ_apply(c, d, x, y=None):
+    """y = P C x (m = n/d outputs)."""
+    import torch
+    n = c.numel()
+    if y is None:
+        y = torch.empty(n // d, device=c.device, dtype=torch.float32)
+    _check(load().cs_circ_apply(_ptr(c, "c"), n, d, _ptr(x, "x", n), _ptr(y, "y", n // d), _stream(c)))
+    return y
+
+
+def circ_apply_T(c, d, r, x=None):
+    """x = C^T P^T r (n outputs)."""
+    import torch
+    n = c.numel()
+    if x is None:
+        x = torch.empty(n, device=c.device, dtype=torch.float32)
+    _check(load().cs_circ_apply_T(_ptr(c, "c"), n, d, _ptr(r, "r", n // d), _ptr(x, "x", n), _stream(c)))
+    return x
+
+
+def circ_norm_bound(c, out=None):
+    """max_k |c_hat_k|^2 as a 1-element device tensor."""
+    import torch
+    if out is None:
+        out = torch.empty(1, device=c.device, dtype=torch.float32)
+    _check(load().cs_circ_norm_bound(_ptr(c, "c"), c.numel(), _ptr(out, "out", 1), _stream(c)))
+    return out
+
+
+def ista_solve(c, d, y, lam, tau, iters, x=None, obj=None):
+    """ISTA (Alg. 1) from x(0) = 0; returns x(iters)."""
+    import torch
+    n = c.numel()
+    if x is None:
+        x = torch.empty(n, device=c.device, dtype=torch.float32)
+    _check(load().cs_ista_solve(_ptr(c, "c"), n, d, _ptr(y, "y", n // d), float(lam), float(tau),
+                                int(iters), _ptr(x, "x", n), _ptr(obj, "obj", iters), _stream(c)))
+    return x
+
+
+def admm_solve(c, d, y, lam, rho, iters, x=None, z=None, u=None, warm=False, obj=None):
+    """ADMM (Alg. 2); returns (x, z, u) after `iters` steps."""
+    import torch
+    n = c.numel()
+    mk = lambda: torch.empty(n, device=c.device, dtype=torch.float32)
+    x = mk() if x is None else x
+    z = mk() if z is None else z
+    u = mk() if u is None else u
+    _check(load().cs_admm_solve(_ptr(c, "c"), n, d, _ptr(y, "y", n // d), float(lam), float(rho),
+                                int(iters), int(bool(warm)), _ptr(x, "x", n), _ptr(z, "z", n),
+                                _ptr(u, "u", n), _ptr(obj, "obj", iters), _stream(c)))
+    return x, z, u
+
+
+def timing_enable(on=True):
+    """Bracket each solver kernel launch with hipEvents (diagnostics)."""
+    _check(load().cs_timing_enable(1 if on else 0))
+
+
+def timing_read(kernel):
+    """(launches, total_ms) of the recorded launches of one kernel; clears them."""
+    n = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    _check(load().cs_timing_read(kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return int(n.value), float(ms.value)
+
+
+def version():
+    return int(load().cs_version())

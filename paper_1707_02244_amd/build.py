@@ -1,0 +1,60 @@
+"""Build libcscirc.so for gfx950 with hipcc (in-tree, no JIT cache).
+
+Each kernel length is compiled in its own translation unit so the objects
+build in parallel; the runtime and the C ABI live in runtime.hip.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libcscirc.so")
+
+ROW_LENGTHS = [16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192]   # pass A (N2)
+COL_LENGTHS = [8, 16, 32, 64, 128, 256, 512, 1024, 2048]            # pass B (N1)
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    # keep the compiler from emitting packed FP32 instructions
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", os.path.join(os.path.dirname(HERE), "include"),
+]
+
+
+def _run(cmd):
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    out = "\n".join(l for l in p.stdout.splitlines() if "packed-fp32-ops" not in l)
+    if p.returncode != 0:
+        raise RuntimeError("command failed (%d): %s\n%s" % (p.returncode, " ".join(cmd), out))
+    return out
+
+
+def build(jobs: int | None = None, verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    units = []
+    for L in ROW_LENGTHS:
+        units.append((os.path.join(CSRC, "inst_passA.hip"), os.path.join(BUILD, "passA_%d.o" % L), ["-DCS_LEN=%d" % L]))
+    for L in COL_LENGTHS:
+        units.append((os.path.join(CSRC, "inst_passB.hip"), os.path.join(BUILD, "passB_%d.o" % L), ["-DCS_LEN=%d" % L]))
+    units.append((os.path.join(CSRC, "runtime.hip"), os.path.join(BUILD, "runtime.o"), []))
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        futs = [ex.submit(_run, [HIPCC] + FLAGS + extra + ["-c", src, "-o", obj]) for src, obj, extra in units]
+        for f in futs:
+            out = f.result()
+            if verbose and out.strip():
+                print(out)
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [u[1] for u in units])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

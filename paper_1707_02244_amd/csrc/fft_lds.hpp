@@ -1,0 +1,154 @@
+// Workgroup-wide complex FFTs held in LDS: Stockham autosort, radix 8 with one
+// radix-4 (or radix-2) stage where log2(L) is not a multiple of three.
+//
+// Algorithm: the self-sorting Stockham formulation (C. Van Loan, Computational
+// Frameworks for the Fast Fourier Transform, SIAM 1992, Section 1.7).  Stage s
+// with span Ns (product of the radices already applied) and radix R reads, for
+// butterfly j < L/R, the R elements j + r*L/R, multiplies element r by
+// W_{Ns*R}^{r*(j mod Ns)}, takes an R-point DFT and writes element r to
+// (j - j mod Ns)*R + (j mod Ns) + r*Ns.  The output is in natural order.
+//
+// Data layout: B independent sequences of length L.
+//   ILV = false: sequence b, element i at buf[b*LD + i]        (rows)
+//   ILV = true : sequence b, element i at buf[i*B + b]         (interleaved
+//                columns; consecutive threads take consecutive b so every
+//                LDS access of a stage is unit-stride across the wave)
+// Each stage loads its butterflies into registers, barriers, then stores in
+// place, so LDS holds one copy of the data.  Twiddles come from a table
+// tw[e] = exp(-2 pi i e / L), e < L, computed on the host in double precision.
+// Forward transforms use exp(-...), inverse ones exp(+...), both unnormalised.
+#pragma once
+#include "cplx.hpp"
+
+namespace cs {
+
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+
+constexpr int stage_radix(int L, int NS) {
+  const int p = ilog2c(L / NS);
+  return (p % 3 == 0) ? 8 : ((p % 3 == 2) ? 4 : (p == 1 ? 2 : 4));
+}
+
+// multiply by the primitive 8th root of unity W8^q (q = 1, 3), forward sign
+// exp(-i pi q / 4) or inverse sign exp(+i pi q / 4).
+template <bool INV>
+__device__ __forceinline__ float2 mul_w8_1(float2 a) {
+  const float s = 0.70710678118654752440f;
+  // fwd: (1 - i)/sqrt2 * (x + iy) = ((x + y) + i(y - x))/sqrt2
+  // inv: (1 + i)/sqrt2 * (x + iy) = ((x - y) + i(x + y))/sqrt2
+  return INV ? c2((a.x - a.y) * s, (a.x + a.y) * s) : c2((a.x + a.y) * s, (a.y - a.x) * s);
+}
+template <bool INV>
+__device__ __forceinline__ float2 mul_w8_3(float2 a) {
+  const float s = 0.70710678118654752440f;
+  // fwd: (-1 - i)/sqrt2 * (x + iy) = ((y - x) - i(x + y))/sqrt2
+  // inv: (-1 + i)/sqrt2 * (x + iy) = (-(x + y) + i(x - y))/sqrt2
+  return INV ? c2(-(a.x + a.y) * s, (a.x - a.y) * s) : c2((a.y - a.x) * s, -(a.x + a.y) * s);
+}
+template <bool INV>
+__device__ __forceinline__ float2 mul_w4(float2 a) {  // W4 = -i (fwd), +i (inv)
+  return INV ? cmuli(a) : cmulmi(a);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(float2* v) {
+  const float2 a = v[0];
+  v[0] = cadd(a, v[1]);
+  v[1] = csub(a, v[1]);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& v0, float2& v1, float2& v2, float2& v3) {
+  const float2 a = cadd(v0, v2), b = csub(v0, v2);
+  const float2 c = cadd(v1, v3), d = mul_w4<INV>(csub(v1, v3));
+  v0 = cadd(a, c);
+  v2 = csub(a, c);
+  v1 = cadd(b, d);
+  v3 = csub(b, d);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2* v) {
+  // even/odd split: E = DFT4(v0, v2, v4, v6), O = DFT4(v1, v3, v5, v7);
+  // y_k = E_k + W8^k O_k, y_{k+4} = E_k - W8^k O_k.
+  float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<INV>(e0, e1, e2, e3);
+  dft4<INV>(o0, o1, o2, o3);
+  o1 = mul_w8_1<INV>(o1);
+  o2 = mul_w4<INV>(o2);
+  o3 = mul_w8_3<INV>(o3);
+  v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2* v) {
+  if constexpr (R == 2) dft2<INV>(v);
+  else if constexpr (R == 4) dft4<INV>(v[0], v[1], v[2], v[3]);
+  else dft8<INV>(v);
+}
+
+template <bool ILV, int B, int LD>
+__device__ __forceinline__ int lds_addr(int b, int i) {
+  if constexpr (ILV) return i * B + b;
+  else return b * LD + i;
+}
+
+template <int L, int B, int T, bool INV, bool ILV, int LD, int NS, int R>
+__device__ __forceinline__ void stockham_stage(float2* __restrict__ buf,
+                                               const float2* __restrict__ tw, int tid) {
+  constexpr int Q = L / R;          // butterflies per sequence
+  constexpr int NBF = B * Q;        // butterflies per stage
+  constexpr int PER = (NBF + T - 1) / T;
+  float2 v[PER][R];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int i = tid + p * T;
+    if (NBF % T == 0 || i < NBF) {
+      const int b = ILV ? (i % B) : (i / Q);
+      const int j = ILV ? (i / B) : (i % Q);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[p][r] = buf[lds_addr<ILV, B, LD>(b, j + r * Q)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int i = tid + p * T;
+    if (NBF % T == 0 || i < NBF) {
+      const int b = ILV ? (i % B) : (i / Q);
+      const int j = ILV ? (i / B) : (i % Q);
+      const int k = j & (NS - 1);
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const float2 w = tw[(r * k) * (L / (NS * R))];
+          v[p][r] = INV ? cmulc(v[p][r], w) : cmul(v[p][r], w);
+        }
+      }
+      dft<R, INV>(v[p]);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[lds_addr<ILV, B, LD>(b, base + r * NS)] = v[p][r];
+    }
+  }
+  __syncthreads();
+}
+
+// B transforms of length L (power of two, >= 2) in place in LDS; all T threads
+// of the workgroup must call it.  Barriers are included before and after
+// every stage's stores; the caller barriers before the first call.
+template <int L, int B, int T, bool INV, bool ILV, int LD, int NS = 1>
+__device__ __forceinline__ void lds_fft(float2* __restrict__ buf,
+                                        const float2* __restrict__ tw, int tid) {
+  if constexpr (NS < L) {
+    constexpr int R = stage_radix(L, NS);
+    stockham_stage<L, B, T, INV, ILV, LD, NS, R>(buf, tw, tid);
+    lds_fft<L, B, T, INV, ILV, LD, NS * R>(buf, tw, tid);
+  }
+}
+
+}  // namespace cs

@@ -1,0 +1,34 @@
+// Pass-A instantiation for one row length N2 = CS_LEN.
+#include "launch.hpp"
+
+#ifndef CS_LEN
+#error "compile with -DCS_LEN=<row length>"
+#endif
+
+namespace cs {
+
+template <>
+hipError_t launch_passA<CS_LEN>(int op, int d2, int grid, const PassAArgs& a, hipStream_t s) {
+  constexpr int L = CS_LEN;
+  const dim3 g(grid), b(kThreads);
+#define CS_GROUP_OP(OPV)                                                              \
+  switch (d2) {                                                                       \
+    case 1: k_passA<L, OPV, 1><<<g, b, 0, s>>>(a); break;                             \
+    case 2: k_passA<L, OPV, 2><<<g, b, 0, s>>>(a); break;                             \
+    case 4: k_passA<L, OPV, 4><<<g, b, 0, s>>>(a); break;                             \
+    case 8: k_passA<L, OPV, 8><<<g, b, 0, s>>>(a); break;                             \
+    default: return hipErrorInvalidValue;                                             \
+  }
+  switch (op) {
+    case A_ISTA: CS_GROUP_OP(A_ISTA); break;
+    case A_ADMM: CS_GROUP_OP(A_ADMM); break;
+    case A_MUL: k_passA<L, A_MUL, 1><<<g, b, 0, s>>>(a); break;
+    case A_MULC: k_passA<L, A_MULC, 1><<<g, b, 0, s>>>(a); break;
+    case A_SPEC: k_passA<L, A_SPEC, 1><<<g, b, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef CS_GROUP_OP
+  return hipGetLastError();
+}
+
+}  // namespace cs

@@ -1,0 +1,366 @@
+// Kernels of the partial-circulant LASSO path (ISTA, Alg. 1; ADMM, Alg. 2).
+//
+// Every product with A = P C or A^T goes through the DFT (circulants are
+// diagonalised by the Fourier matrix, Section 4.2).  A length-n real signal x
+// is packed as the complex sequence z_j = x_{2j} + i x_{2j+1}, j < N = n/2,
+// and transformed with a four-step FFT N = N1 * N2:
+//
+//   pass B ("columns", this file's k_passB): for each column j2, an N1-point
+//     FFT over j1 of z[N2*j1 + j2], times W_N^{j2*k1}; stored as Y[k1][j2].
+//   pass A ("rows", k_passA): for a row k1, an N2-point FFT over j2 gives the
+//     packed spectrum Z at bins k = k1 + N1*k2 in position k2.
+//
+// The real spectrum follows from Z by the usual split
+//   X_k = P + W_n^k Q,  X_{N-k} = conj(P - W_n^k Q),
+//   P = (Z_k + conj Z_{N-k})/2,  Q = -i (Z_k - conj Z_{N-k})/2,
+// and bins k and N-k sit in rows k1 and N1-k1.  Decimation by d (P keeps every
+// d-th sample) aliases the n-point spectrum onto m = n/d bins: the m-point
+// spectrum of P w is (1/d) sum_l W_{k'+l m}.  When N1 divides m, the d bins
+// of an alias class lie in rows k1 and N1-k1 too, so one workgroup owning that
+// row pair sees every bin its frequency-domain update touches.
+//
+// The frequency-domain updates (per alias class k', with a = the class's
+// bins in [0, N), b = the mirrored bins N - k'- l m, S = A x in the m-point
+// domain, c_hat = DFT_n(c), Y_hat = DFT_m(y)):
+//   ISTA (Alg. 1 with the tau*lam threshold):
+//     S = (sum_a c_a X_a + conj(sum_b c_b X_b)) / d,  E = Y_hat - S,
+//     D_a = tau conj(c_a) E,  D_b = tau conj(c_b) conj(E)   (= DFT of tau A^T r)
+//     x+ = eta_{tau lam}(x + IDFT_n D)
+//   The iterate x stays in the time domain and only the step tau A^T r
+//   goes through the inverse transform: carrying x itself through a forward
+//   and inverse FP32 FFT every iteration adds round-off that accumulates
+//   along ISTA's slowly contracting directions.
+//   ADMM x-update (Alg. 2, with (A^T A + rho I)^{-1} applied by Woodbury:
+//     (A^T A + rho I)^{-1} = rho^{-1}[I - A^T (rho I + A A^T)^{-1} A], and
+//     A A^T is the m x m circulant with eigenvalues
+//     Lam_k' = (1/d) sum_class |c_hat|^2):
+//     Q_a = conj(c_a) Y_hat + rho X_a,  Q_b = conj(c_b) conj(Y_hat) + rho X_b,
+//     T = (sum_a c_a Q_a + conj(sum_b c_b Q_b)) / (d rho + sum |c|^2),
+//     X'_a = (Q_a - conj(c_a) T)/rho,  X'_b = (Q_b - conj(c_b) conj(T))/rho,
+//   where X is the spectrum of z - u.
+// The time-domain steps (soft threshold, Eq. 4; ADMM's z and u updates) are
+// fused into pass B between its inverse and forward column transforms.
+#pragma once
+#include "cplx.hpp"
+#include "fft_lds.hpp"
+
+namespace cs {
+
+constexpr int kThreads = 256;
+constexpr int kColsPerBlock = 8;   // pass B: adjacent columns per workgroup (64 B runs)
+constexpr int kPadA = 4;           // pass A: float2 padding between the two rows
+
+enum OpA : int {
+  A_ISTA = 0,   // ISTA frequency update (alias classes)
+  A_ADMM = 1,   // ADMM Woodbury x-update (alias classes)
+  A_MUL = 2,    // multiply by c_hat      (C x)
+  A_MULC = 3,   // multiply by conj(c_hat) (C^T x)
+  A_SPEC = 4,   // write the half spectrum X_k, k in [0, N], to a table
+};
+
+enum ModeB : int {
+  B_FWD_REAL = 0,  // load real x (n)                 -> forward -> Y
+  B_FWD_UP = 1,    // load P^T r (r has m = n/d)      -> forward -> Y
+  B_FWD_ZMU = 2,   // load z - u (n each)             -> forward -> Y
+  B_ISTA = 3,      // Y (step) -> inverse -> x += step, threshold -> forward -> Y
+  B_ADMM = 4,      // Y -> inverse -> z, u update -> forward(z - u) -> Y (or write x, z)
+  B_OUT_ALL = 5,   // Y -> inverse -> write all n reals
+  B_OUT_DEC = 6,   // Y -> inverse -> write every d-th real (m values)
+};
+
+struct PassAArgs {
+  float2* Y;               // [N1][N2] workspace (in and out)
+  const float2* chat;      // c_hat, bin k1 + N1*k2 at [k1*N2 + k2], Nyquist at [N]
+  const float2* yhat;      // DFT_n(P^T y) in the same layout (= Y_hat at k' < m)
+  float2* table;           // A_SPEC destination, same layout
+  const float2* tw2;       // W_{N2}^e, e < N2
+  const float2* twk1;      // W_n^{k1}, k1 < N1
+  const float2* twp;       // W_{2 N2}^p, p < N2   (W_n^{N1 p})
+  int N1;
+  int M;                   // m / N1: alias classes per row
+  int N;                   // N1 * N2
+  float inv_n;             // 1/n
+  float inv_d;             // 1/d
+  float tau;               // ISTA step
+  float rho, inv_rho, d_rho;
+};
+
+struct PassBArgs {
+  float2* Y;               // [N1][N2] workspace
+  const float2* tw1;       // W_{N1}^e, e < N1
+  const float2* twlo;      // W_N^e, e < 2^lo_bits
+  const float2* twhi;      // W_N^{e * 2^lo_bits}, e < N >> lo_bits
+  int lo_bits;
+  int N2;
+  int N;
+  int d;
+  const float* in0;        // B_FWD_REAL: x; B_FWD_UP: r; B_FWD_ZMU: z
+  const float* in1;        // B_FWD_ZMU: u
+  float* out0;             // B_ADMM last: x; B_OUT_*: output
+  float* out1;             // B_ADMM last: z
+  float* u;                // state (n), read and written: B_ISTA x, B_ADMM u
+  float thr;               // threshold (ISTA: tau*lam; ADMM: lam/rho)
+  int last;                // final iteration: write outputs, skip the forward
+};
+
+// ---------------------------------------------------------------------------
+// Four-step twiddle W_N^e from a two-level table.
+__device__ __forceinline__ float2 tw_N(const PassBArgs& a, int e) {
+  e &= (a.N - 1);
+  return cmul(a.twlo[e & ((1 << a.lo_bits) - 1)], a.twhi[e >> a.lo_bits]);
+}
+
+// ---------------------------------------------------------------------------
+// Pass A.  Workgroup w owns rows {w, N1 - w}; workgroup 0 owns the two rows
+// that are their own mirror images, {0, N1/2}.  Rows are held in LDS slots 0
+// and 1.
+template <int N2, int OP, int D2>
+__global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
+  constexpr int T = kThreads;
+  constexpr int LD = N2 + kPadA;
+  __shared__ float2 lds[2 * LD];
+  const int tid = threadIdx.x;
+  const int w = blockIdx.x;
+  const int N1 = a.N1;
+  const int ra = w;                          // row in slot 0
+  const int rb = w ? (N1 - w) : (N1 >> 1);   // row in slot 1
+
+  for (int i = tid; i < 2 * N2; i += T) {
+    const int s = i / N2, p = i % N2;
+    lds[s * LD + p] = a.Y[(size_t)(s ? rb : ra) * N2 + p];
+  }
+  __syncthreads();
+  lds_fft<N2, 2, T, false, false, LD>(lds, a.tw2, tid);
+
+  if constexpr (OP == A_ISTA || OP == A_ADMM) {
+    // Alias classes.  For w > 0: class k' = w + N1*k2, k2 < M, has a-bins at
+    // row w positions k2 + l*M and b-bins at row N1-w positions N2-1-k2-l*M.
+    // For w = 0: row 0 classes k2 in [0, M/2] (b positions (N2 - p) mod N2;
+    // k2 = 0 and M/2 are their own mirror: write the a side only), then row
+    // N1/2 classes k2 in [0, M/2) (b positions N2-1-p in the same row).
+    const int M = a.M;
+    const int ng = w ? M : (M + 1);
+    for (int g = tid; g < ng; g += T) {
+      int sa, sb, rowa, k2, mode;  // mode 0: pair rows, 1: row 0, 2: row N1/2
+      if (w) { sa = 0; sb = 1; rowa = w; k2 = g; mode = 0; }
+      else if (g <= (M >> 1)) { sa = 0; sb = 0; rowa = 0; k2 = g; mode = 1; }
+      else { sa = 1; sb = 1; rowa = N1 >> 1; k2 = g - (M >> 1) - 1; mode = 2; }
+      const int rowb = (mode == 0) ? (N1 - w) : rowa;
+      const bool write_b = !(mode == 1 && (k2 == 0 || k2 == (M >> 1)));
+      float2 Xa[D2], Xb[D2], ca[D2], cb[D2], wa[D2];
+      int pa[D2], qb[D2];
+#pragma unroll
+      for (int l = 0; l < D2; ++l) {
+        const int p = k2 + l * M;
+        const int q = (mode == 1) ? ((N2 - p) & (N2 - 1)) : (N2 - 1 - p);
+        pa[l] = p; qb[l] = q;
+        const float2 za = lds[sa * LD + p];
+        const float2 zb = lds[sb * LD + q];
+        const float2 wt = cmul(a.twk1[rowa], a.twp[p]);
+        wa[l] = wt;
+        const float2 zbc = cconj(zb);
+        const float2 P = cscale(cadd(za, zbc), 0.5f);
+        const float2 Q = cscale(cmulmi(csub(za, zbc)), 0.5f);
+        const float2 wq = cmul(wt, Q);
+        Xa[l] = cadd(P, wq);
+        Xb[l] = cconj(csub(P, wq));
+        ca[l] = a.chat[(size_t)rowa * N2 + p];
+        cb[l] = (mode == 1 && p == 0) ? a.chat[a.N] : a.chat[(size_t)rowb * N2 + q];
+      }
+      const float2 yk = a.yhat[(size_t)rowa * N2 + k2];
+      float2 Va[D2], Vb[D2];
+      if constexpr (OP == A_ISTA) {
+        float2 sa_ = c2(0.f, 0.f), sb_ = c2(0.f, 0.f);
+#pragma unroll
+        for (int l = 0; l < D2; ++l) { sa_ = cadd(sa_, cmul(ca[l], Xa[l])); sb_ = cadd(sb_, cmul(cb[l], Xb[l])); }
+        const float2 S = cscale(cadd(sa_, cconj(sb_)), a.inv_d);
+        const float2 E = cscale(csub(yk, S), a.tau);
+        const float2 Ec = cconj(E);
+#pragma unroll
+        for (int l = 0; l < D2; ++l) {
+          Va[l] = cconjmul(ca[l], E);
+          Vb[l] = cconjmul(cb[l], Ec);
+        }
+      } else {
+        float2 Qa[D2], Qb[D2];
+        const float2 ykc = cconj(yk);
+        float2 ra_ = c2(0.f, 0.f), rb_ = c2(0.f, 0.f);
+        float lam = a.d_rho;
+#pragma unroll
+        for (int l = 0; l < D2; ++l) {
+          Qa[l] = cadd(cconjmul(ca[l], yk), cscale(Xa[l], a.rho));
+          Qb[l] = cadd(cconjmul(cb[l], ykc), cscale(Xb[l], a.rho));
+          ra_ = cadd(ra_, cmul(ca[l], Qa[l]));
+          rb_ = cadd(rb_, cmul(cb[l], Qb[l]));
+          lam += cabs2(ca[l]) + cabs2(cb[l]);
+        }
+        const float2 Tq = cscale(cadd(ra_, cconj(rb_)), 1.0f / lam);
+        const float2 Tc = cconj(Tq);
+#pragma unroll
+        for (int l = 0; l < D2; ++l) {
+          Va[l] = cscale(csub(Qa[l], cconjmul(ca[l], Tq)), a.inv_rho);
+          Vb[l] = cscale(csub(Qb[l], cconjmul(cb[l], Tc)), a.inv_rho);
+        }
+      }
+      // inverse split, scaled by 1/n (1/2 of the split times 1/N of the inverse)
+#pragma unroll
+      for (int l = 0; l < D2; ++l) {
+        const float2 vbc = cconj(Vb[l]);
+        const float2 E_ = cscale(cadd(Va[l], vbc), a.inv_n);
+        const float2 O_ = cscale(cmulc(csub(Va[l], vbc), wa[l]), a.inv_n);
+        lds[sa * LD + pa[l]] = cadd(E_, cmuli(O_));
+        if (write_b) lds[sb * LD + qb[l]] = cconj(csub(E_, cmuli(O_)));
+      }
+    }
+  } else {
+    // Pointwise modes, by split pairs (k, N - k).  w > 0: slot 0 position p
+    // pairs with slot 1 position N2-1-p.  w = 0: row 0 positions p in
+    // [0, N2/2] pair with (N2 - p) mod N2 (p = 0 and N2/2 pair with
+    // themselves), row N1/2 positions p < N2/2 pair with N2-1-p.
+    const int np = w ? N2 : (N2 + 1);
+    for (int g = tid; g < np; g += T) {
+      int sa, sb, rowa, p, mode;
+      if (w) { sa = 0; sb = 1; rowa = w; p = g; mode = 0; }
+      else if (g <= (N2 >> 1)) { sa = 0; sb = 0; rowa = 0; p = g; mode = 1; }
+      else { sa = 1; sb = 1; rowa = N1 >> 1; p = g - (N2 >> 1) - 1; mode = 2; }
+      const int rowb = (mode == 0) ? (N1 - w) : rowa;
+      const int q = (mode == 1) ? ((N2 - p) & (N2 - 1)) : (N2 - 1 - p);
+      const bool write_b = !(mode == 1 && (p == 0 || p == (N2 >> 1)));
+      const float2 za = lds[sa * LD + p];
+      const float2 zb = lds[sb * LD + q];
+      const float2 wt = cmul(a.twk1[rowa], a.twp[p]);
+      const float2 zbc = cconj(zb);
+      const float2 P = cscale(cadd(za, zbc), 0.5f);
+      const float2 Q = cscale(cmulmi(csub(za, zbc)), 0.5f);
+      const float2 wq = cmul(wt, Q);
+      const float2 Xa = cadd(P, wq);
+      const float2 Xb = cconj(csub(P, wq));
+      if constexpr (OP == A_SPEC) {
+        a.table[(size_t)rowa * N2 + p] = Xa;
+        if (write_b) a.table[(size_t)rowb * N2 + q] = Xb;
+        if (mode == 1 && p == 0) a.table[a.N] = Xb;
+      } else {
+        const float2 ca = a.chat[(size_t)rowa * N2 + p];
+        const float2 cb = (mode == 1 && p == 0) ? a.chat[a.N] : a.chat[(size_t)rowb * N2 + q];
+        float2 Va, Vb;
+        if constexpr (OP == A_MUL) { Va = cmul(ca, Xa); Vb = cmul(cb, Xb); }
+        else { Va = cconjmul(ca, Xa); Vb = cconjmul(cb, Xb); }
+        const float2 vbc = cconj(Vb);
+        const float2 E_ = cscale(cadd(Va, vbc), a.inv_n);
+        const float2 O_ = cscale(cmulc(csub(Va, vbc), wt), a.inv_n);
+        lds[sa * LD + p] = cadd(E_, cmuli(O_));
+        if (write_b) lds[sb * LD + q] = cconj(csub(E_, cmuli(O_)));
+      }
+    }
+  }
+  if constexpr (OP != A_SPEC) {
+    __syncthreads();
+    lds_fft<N2, 2, T, true, false, LD>(lds, a.tw2, tid);
+    for (int i = tid; i < 2 * N2; i += T) {
+      const int s = i / N2, p = i % N2;
+      a.Y[(size_t)(s ? rb : ra) * N2 + p] = lds[s * LD + p];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass B.  Workgroup b owns columns j2 in [b*CB, b*CB + CB); LDS holds them
+// interleaved, element (column c, index i) at [i*CB + c].
+template <int N1, int MODE>
+__global__ __launch_bounds__(kThreads) void k_passB(PassBArgs a) {
+  constexpr int T = kThreads;
+  constexpr int CB = kColsPerBlock;
+  constexpr int NE = N1 * CB;
+  __shared__ float2 lds[NE];
+  const int tid = threadIdx.x;
+  const int j2_0 = blockIdx.x * CB;
+  const int N2 = a.N2;
+  constexpr bool HAS_INV = (MODE == B_ISTA || MODE == B_ADMM || MODE == B_OUT_ALL || MODE == B_OUT_DEC);
+
+  if constexpr (HAS_INV) {
+    for (int i = tid; i < NE; i += T) {
+      const int k1 = i / CB, c = i % CB;
+      const int j2 = j2_0 + c;
+      lds[i] = cmulc(a.Y[(size_t)k1 * N2 + j2], tw_N(a, j2 * k1));
+    }
+    __syncthreads();
+    lds_fft<N1, CB, T, true, true, N1>(lds, a.tw1, tid);
+    // time domain: lds[j1*CB + c] = (x_{2j}, x_{2j+1}), j = N2*j1 + j2_0 + c
+    bool fwd = true;
+    if constexpr (MODE == B_ISTA) {
+      // lds holds tau A^T r in the time domain; a.u is the iterate x.
+      const float thr = a.thr;
+      float2* xs = reinterpret_cast<float2*>(a.u);
+      for (int i = tid; i < NE; i += T) {
+        const int j1 = i / CB, c = i % CB;
+        const size_t j = (size_t)j1 * N2 + j2_0 + c;
+        const float2 v = cadd(xs[j], lds[i]);
+        const float2 x = c2(soft(v.x, thr), soft(v.y, thr));
+        xs[j] = x;
+        lds[i] = x;
+      }
+      fwd = !a.last;
+    } else if constexpr (MODE == B_ADMM) {
+      const float thr = a.thr;
+      float2* u = reinterpret_cast<float2*>(a.u);
+      for (int i = tid; i < NE; i += T) {
+        const int j1 = i / CB, c = i % CB;
+        const size_t j = (size_t)j1 * N2 + j2_0 + c;
+        const float2 x = lds[i];
+        const float2 u0 = u[j];
+        const float2 xu = cadd(x, u0);
+        const float2 z = c2(soft(xu.x, thr), soft(xu.y, thr));
+        const float2 u1 = csub(xu, z);
+        u[j] = u1;
+        if (a.last) {
+          reinterpret_cast<float2*>(a.out0)[j] = x;
+          reinterpret_cast<float2*>(a.out1)[j] = z;
+        } else {
+          lds[i] = csub(z, u1);
+        }
+      }
+      fwd = !a.last;
+    } else if constexpr (MODE == B_OUT_ALL) {
+      for (int i = tid; i < NE; i += T) {
+        const int j1 = i / CB, c = i % CB;
+        const size_t j = (size_t)j1 * N2 + j2_0 + c;
+        reinterpret_cast<float2*>(a.out0)[j] = lds[i];
+      }
+      fwd = false;
+    } else {  // B_OUT_DEC: real sample 2j is kept when 2j % d == 0 (d even)
+      const int h = a.d >> 1;
+      for (int i = tid; i < NE; i += T) {
+        const int j1 = i / CB, c = i % CB;
+        const size_t j = (size_t)j1 * N2 + j2_0 + c;
+        if ((j % h) == 0) a.out0[j / h] = lds[i].x;
+      }
+      fwd = false;
+    }
+    if (!fwd) return;
+    __syncthreads();
+  } else {
+    for (int i = tid; i < NE; i += T) {
+      const int j1 = i / CB, c = i % CB;
+      const size_t j = (size_t)j1 * N2 + j2_0 + c;
+      float2 v;
+      if constexpr (MODE == B_FWD_REAL) {
+        v = reinterpret_cast<const float2*>(a.in0)[j];
+      } else if constexpr (MODE == B_FWD_UP) {
+        const int h = a.d >> 1;
+        v = c2((j % h) == 0 ? a.in0[j / h] : 0.0f, 0.0f);
+      } else {
+        v = csub(reinterpret_cast<const float2*>(a.in0)[j], reinterpret_cast<const float2*>(a.in1)[j]);
+      }
+      lds[i] = v;
+    }
+    __syncthreads();
+  }
+  lds_fft<N1, CB, T, false, true, N1>(lds, a.tw1, tid);
+  for (int i = tid; i < NE; i += T) {
+    const int k1 = i / CB, c = i % CB;
+    const int j2 = j2_0 + c;
+    a.Y[(size_t)k1 * N2 + j2] = cmul(lds[i], tw_N(a, j2 * k1));
+  }
+}
+
+}  // namespace cs

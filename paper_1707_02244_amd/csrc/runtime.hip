@@ -1,0 +1,491 @@
+// Host runtime and C ABI of the partial-circulant LASSO library.
+//
+// A plan per (device, n, d) holds the twiddle tables (computed in double
+// precision with std::cos / std::sin and rounded to float) and the
+// workspace: the four-step spectrum buffer Y (N = n/2 complex), the table of
+// c_hat (N + 1 complex, bin k1 + N1*k2 at [k1*N2 + k2], Nyquist at [N]) and
+// the table of DFT_n(P^T y) (same layout; its bins k' < m are y's m-point
+// spectrum).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/cscirc.h"
+#include "launch.hpp"
+
+namespace cs {
+namespace {
+
+thread_local std::string g_err;
+
+cs_status fail(cs_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+cs_status fail(cs_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define CS_HIP(call)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(CS_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));           \
+  } while (0)
+
+constexpr int64_t kMinN = 256;
+constexpr int64_t kMaxN = int64_t(1) << 25;
+constexpr int kMaxN1 = 2048;
+
+int ilog2(int64_t v) {
+  int r = 0;
+  while ((int64_t(1) << r) < v) ++r;
+  return r;
+}
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+struct Plan {
+  int dev = 0;
+  int64_t n = 0;
+  int d = 0;
+  int N = 0, N1 = 0, N2 = 0, M = 0, lo_bits = 0;
+  float2* mem = nullptr;
+  float2 *Y = nullptr, *chat = nullptr, *yhat = nullptr;
+  float2 *tw1 = nullptr, *tw2 = nullptr, *twlo = nullptr, *twhi = nullptr;
+  float2 *twk1 = nullptr, *twp = nullptr;
+  float* scal = nullptr;   // small device scalars (norm bound)
+  ~Plan() {
+    if (mem) (void)hipFree(mem);
+  }
+};
+
+std::mutex g_mu;
+std::map<std::tuple<int, int64_t, int>, std::unique_ptr<Plan>> g_plans;
+
+// exp(-2 pi i e / L) in double precision, rounded to float.
+float2 root(int64_t e, int64_t L) {
+  const double a = -2.0 * M_PI * double(e % L) / double(L);
+  return make_float2(float(std::cos(a)), float(std::sin(a)));
+}
+
+cs_status get_plan(int64_t n, int d, Plan** out) {
+  int dev = 0;
+  CS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_tuple(dev, n, d);
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    *out = it->second.get();
+    return CS_OK;
+  }
+  auto p = std::make_unique<Plan>();
+  p->dev = dev;
+  p->n = n;
+  p->d = d;
+  p->N = int(n / 2);
+  const int pN = ilog2(p->N);
+  p->N1 = 1 << (pN / 2);
+  if (p->N1 > kMaxN1) p->N1 = kMaxN1;
+  p->N2 = p->N / p->N1;
+  p->M = int((n / d) / p->N1);
+  p->lo_bits = (pN + 1) / 2;
+  const int64_t nlo = int64_t(1) << p->lo_bits, nhi = int64_t(p->N) >> p->lo_bits;
+  // layout (float2 elements, each block rounded up to 64)
+  auto up = [](int64_t v) { return (v + 63) & ~int64_t(63); };
+  const int64_t oY = 0, oC = oY + up(p->N), oYh = oC + up(p->N + 1), oT1 = oYh + up(p->N + 1);
+  const int64_t oT2 = oT1 + up(p->N1), oLo = oT2 + up(p->N2), oHi = oLo + up(nlo);
+  const int64_t oK1 = oHi + up(nhi), oP = oK1 + up(p->N1), oS = oP + up(p->N2);
+  const int64_t total = oS + 64;
+  hipError_t e = hipMalloc(&p->mem, size_t(total) * sizeof(float2));
+  if (e != hipSuccess) return fail(CS_ENOMEM, "hipMalloc of %lld bytes for plan n=%lld d=%d failed: %s",
+                                   (long long)(total * sizeof(float2)), (long long)n, d, hipGetErrorString(e));
+  float2* b = p->mem;
+  p->Y = b + oY; p->chat = b + oC; p->yhat = b + oYh;
+  p->tw1 = b + oT1; p->tw2 = b + oT2; p->twlo = b + oLo; p->twhi = b + oHi;
+  p->twk1 = b + oK1; p->twp = b + oP; p->scal = reinterpret_cast<float*>(b + oS);
+  std::vector<float2> h(size_t(total - oT1));
+  auto put = [&](int64_t off, int64_t cnt, auto fn) {
+    for (int64_t i = 0; i < cnt; ++i) h[size_t(off - oT1 + i)] = fn(i);
+  };
+  put(oT1, p->N1, [&](int64_t i) { return root(i, p->N1); });
+  put(oT2, p->N2, [&](int64_t i) { return root(i, p->N2); });
+  put(oLo, nlo, [&](int64_t i) { return root(i, p->N); });
+  put(oHi, nhi, [&](int64_t i) { return root(i * nlo, p->N); });
+  put(oK1, p->N1, [&](int64_t i) { return root(i, n); });
+  put(oP, p->N2, [&](int64_t i) { return root(i, 2 * int64_t(p->N2)); });
+  e = hipMemcpy(b + oT1, h.data(), h.size() * sizeof(float2), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(CS_EHIP, "hipMemcpy of plan tables failed: %s", hipGetErrorString(e));
+  *out = p.get();
+  g_plans[key] = std::move(p);
+  return CS_OK;
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launchA(const Plan& P, int op, const PassAArgs& a, hipStream_t s) {
+  const int grid = P.N1 / 2;
+  const int d2 = P.d / 2;
+  switch (P.N2) {
+    case 16: return launch_passA<16>(op, d2, grid, a, s);
+    case 32: return launch_passA<32>(op, d2, grid, a, s);
+    case 64: return launch_passA<64>(op, d2, grid, a, s);
+    case 128: return launch_passA<128>(op, d2, grid, a, s);
+    case 256: return launch_passA<256>(op, d2, grid, a, s);
+    case 512: return launch_passA<512>(op, d2, grid, a, s);
+    case 1024: return launch_passA<1024>(op, d2, grid, a, s);
+    case 2048: return launch_passA<2048>(op, d2, grid, a, s);
+    case 4096: return launch_passA<4096>(op, d2, grid, a, s);
+    case 8192: return launch_passA<8192>(op, d2, grid, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launchB(const Plan& P, int mode, const PassBArgs& a, hipStream_t s) {
+  const int grid = P.N2 / kColsPerBlock;
+  switch (P.N1) {
+    case 8: return launch_passB<8>(mode, grid, a, s);
+    case 16: return launch_passB<16>(mode, grid, a, s);
+    case 32: return launch_passB<32>(mode, grid, a, s);
+    case 64: return launch_passB<64>(mode, grid, a, s);
+    case 128: return launch_passB<128>(mode, grid, a, s);
+    case 256: return launch_passB<256>(mode, grid, a, s);
+    case 512: return launch_passB<512>(mode, grid, a, s);
+    case 1024: return launch_passB<1024>(mode, grid, a, s);
+    case 2048: return launch_passB<2048>(mode, grid, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Optional per-launch timing (diagnostics): each solver kernel launch is
+// bracketed by two hipEvents on its own stream.
+struct TimedLaunch {
+  int kind;
+  hipEvent_t start, stop;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimedLaunch> g_timed;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t take_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+enum TimedKind { T_A_ISTA = 0, T_B_ISTA, T_A_ADMM, T_B_ADMM, T_COUNT };
+const char* kTimedNames[T_COUNT] = {"passA_ista", "passB_ista", "passA_admm", "passB_admm"};
+
+template <class F>
+hipError_t timed(int kind, hipStream_t s, F&& launch) {
+  if (!g_timing) return launch();
+  std::lock_guard<std::mutex> lk(g_tmu);
+  TimedLaunch t{kind, take_event(), take_event()};
+  if (!t.start || !t.stop) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(t.start, s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(t.stop, s);
+  if (e != hipSuccess) return e;
+  g_timed.push_back(t);
+  return hipSuccess;
+}
+
+PassAArgs argsA(const Plan& P) {
+  PassAArgs a{};
+  a.Y = P.Y; a.chat = P.chat; a.yhat = P.yhat; a.table = nullptr;
+  a.tw2 = P.tw2; a.twk1 = P.twk1; a.twp = P.twp;
+  a.N1 = P.N1; a.M = P.M; a.N = P.N;
+  a.inv_n = float(1.0 / double(P.n));
+  a.inv_d = float(1.0 / double(P.d));
+  return a;
+}
+
+PassBArgs argsB(const Plan& P) {
+  PassBArgs b{};
+  b.Y = P.Y; b.tw1 = P.tw1; b.twlo = P.twlo; b.twhi = P.twhi; b.lo_bits = P.lo_bits;
+  b.N2 = P.N2; b.N = P.N; b.d = P.d;
+  return b;
+}
+
+#define CS_LAUNCH(call)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) return fail(CS_EHIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
+  } while (0)
+
+// c_hat table from c (pass B forward on the real signal, pass A split).
+cs_status setup_chat(const Plan& P, const float* c, hipStream_t s) {
+  PassBArgs b = argsB(P);
+  b.in0 = c;
+  CS_LAUNCH(launchB(P, B_FWD_REAL, b, s));
+  PassAArgs a = argsA(P);
+  a.table = P.chat;
+  CS_LAUNCH(launchA(P, A_SPEC, a, s));
+  return CS_OK;
+}
+
+// DFT_n(P^T y) table (its first m bins are the m-point spectrum of y).
+cs_status setup_yhat(const Plan& P, const float* y, hipStream_t s) {
+  PassBArgs b = argsB(P);
+  b.in0 = y;
+  CS_LAUNCH(launchB(P, B_FWD_UP, b, s));
+  PassAArgs a = argsA(P);
+  a.table = P.yhat;
+  CS_LAUNCH(launchA(P, A_SPEC, a, s));
+  return CS_OK;
+}
+
+__global__ void k_fill(float* __restrict__ p, size_t count, float v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) p[i] = v;
+}
+
+cs_status fill(float* p, size_t count, float v, hipStream_t s) {
+  if (count == 0) return CS_OK;
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  k_fill<<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(p, count, v);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
+}
+
+__global__ void k_max_abs2(const float2* __restrict__ t, int count, float* __restrict__ out) {
+  __shared__ float red[256];
+  float m = 0.0f;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+    m = fmaxf(m, cabs2(t[i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + k]);
+    __syncthreads();
+  }
+  // non-negative floats order like their bit patterns
+  if (threadIdx.x == 0) atomicMax(reinterpret_cast<unsigned int*>(out), __float_as_uint(red[0]));
+}
+
+cs_status check_common(const void* c, int64_t n, int d) {
+  if (!c) return fail(CS_EINVAL, "c is NULL");
+  if (!is_pow2(n) || n < kMinN || n > kMaxN)
+    return fail(CS_EINVAL, "n=%lld must be a power of two in [%lld, %lld]", (long long)n,
+                (long long)kMinN, (long long)kMaxN);
+  if (d != 2 && d != 4 && d != 8 && d != 16)
+    return fail(CS_EINVAL, "d=%d must be 2, 4, 8 or 16", d);
+  return CS_OK;
+}
+
+bool finite(float v) { return std::isfinite(v); }
+
+}  // namespace
+}  // namespace cs
+
+using namespace cs;
+
+extern "C" {
+
+const char* cs_last_error(void) { return g_err.c_str(); }
+
+int32_t cs_version(void) { return 100; }
+
+cs_status cs_timing_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_timing = (on != 0);
+  g_err.clear();
+  return CS_OK;
+}
+
+cs_status cs_timing_read(const char* kernel, int64_t* launches, double* total_ms) {
+  if (!kernel || !launches || !total_ms) return fail(CS_EINVAL, "NULL argument");
+  int kind = -1;
+  for (int k = 0; k < T_COUNT; ++k)
+    if (std::strcmp(kernel, kTimedNames[k]) == 0) kind = k;
+  if (kind < 0) return fail(CS_EINVAL, "unknown kernel name '%s'", kernel);
+  std::lock_guard<std::mutex> lk(g_tmu);
+  int64_t cnt = 0;
+  double tot = 0.0;
+  std::vector<TimedLaunch> keep;
+  for (auto& t : g_timed) {
+    if (t.kind != kind) {
+      keep.push_back(t);
+      continue;
+    }
+    hipError_t e = hipEventSynchronize(t.stop);
+    if (e != hipSuccess) return fail(CS_EHIP, "hipEventSynchronize failed: %s", hipGetErrorString(e));
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, t.start, t.stop);
+    if (e != hipSuccess) return fail(CS_EHIP, "hipEventElapsedTime failed: %s", hipGetErrorString(e));
+    tot += ms;
+    ++cnt;
+    g_event_pool.push_back(t.start);
+    g_event_pool.push_back(t.stop);
+  }
+  g_timed.swap(keep);
+  *launches = cnt;
+  *total_ms = tot;
+  g_err.clear();
+  return CS_OK;
+}
+
+cs_status cs_circ_apply(const float* c, int64_t n, int32_t d, const float* x, float* y,
+                        cs_stream stream) {
+  cs_status st = check_common(c, n, d);
+  if (st != CS_OK) return st;
+  if (!x || !y) return fail(CS_EINVAL, "x or y is NULL");
+  Plan* P = nullptr;
+  if ((st = get_plan(n, d, &P)) != CS_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
+  PassBArgs b = argsB(*P);
+  b.in0 = x;
+  CS_LAUNCH(launchB(*P, B_FWD_REAL, b, s));
+  CS_LAUNCH(launchA(*P, A_MUL, argsA(*P), s));
+  b = argsB(*P);
+  b.out0 = y;
+  CS_LAUNCH(launchB(*P, B_OUT_DEC, b, s));
+  g_err.clear();
+  return CS_OK;
+}
+
+cs_status cs_circ_apply_T(const float* c, int64_t n, int32_t d, const float* r, float* x,
+                          cs_stream stream) {
+  cs_status st = check_common(c, n, d);
+  if (st != CS_OK) return st;
+  if (!r || !x) return fail(CS_EINVAL, "r or x is NULL");
+  Plan* P = nullptr;
+  if ((st = get_plan(n, d, &P)) != CS_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
+  PassBArgs b = argsB(*P);
+  b.in0 = r;
+  CS_LAUNCH(launchB(*P, B_FWD_UP, b, s));
+  CS_LAUNCH(launchA(*P, A_MULC, argsA(*P), s));
+  b = argsB(*P);
+  b.out0 = x;
+  CS_LAUNCH(launchB(*P, B_OUT_ALL, b, s));
+  g_err.clear();
+  return CS_OK;
+}
+
+cs_status cs_circ_norm_bound(const float* c, int64_t n, float* out, cs_stream stream) {
+  cs_status st = check_common(c, n, 2);
+  if (st != CS_OK) return st;
+  if (!out) return fail(CS_EINVAL, "out is NULL");
+  Plan* P = nullptr;
+  if ((st = get_plan(n, 2, &P)) != CS_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
+  if ((st = fill(out, 1, 0.0f, s)) != CS_OK) return st;
+  int blocks = (P->N + 1 + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  k_max_abs2<<<dim3(blocks), dim3(256), 0, s>>>(P->chat, P->N + 1, out);
+  CS_HIP(hipGetLastError());
+  g_err.clear();
+  return CS_OK;
+}
+
+cs_status cs_ista_solve(const float* c, int64_t n, int32_t d, const float* y, float lambda,
+                        float tau, int32_t iters, float* x, float* obj, cs_stream stream) {
+  cs_status st = check_common(c, n, d);
+  if (st != CS_OK) return st;
+  if (!y || !x) return fail(CS_EINVAL, "y or x is NULL");
+  if (!finite(lambda) || lambda < 0.0f) return fail(CS_EINVAL, "lambda=%g must be finite and >= 0", lambda);
+  if (!finite(tau) || tau <= 0.0f) return fail(CS_EINVAL, "tau=%g must be finite and > 0", tau);
+  if (iters < 0) return fail(CS_EINVAL, "iters=%d must be >= 0", iters);
+  if (obj) return fail(CS_ENOTSUP, "objective trace is not supported; pass obj = NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (iters == 0) {
+    if ((st = fill(x, size_t(n), 0.0f, s)) != CS_OK) return st;
+    g_err.clear();
+    return CS_OK;
+  }
+  Plan* P = nullptr;
+  if ((st = get_plan(n, d, &P)) != CS_OK) return st;
+  if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
+  if ((st = setup_yhat(*P, y, s)) != CS_OK) return st;
+  if ((st = fill(reinterpret_cast<float*>(P->Y), size_t(P->N) * 2, 0.0f, s)) != CS_OK) return st;
+  if ((st = fill(x, size_t(n), 0.0f, s)) != CS_OK) return st;
+  PassAArgs a = argsA(*P);
+  a.tau = tau;
+  PassBArgs b = argsB(*P);
+  b.thr = tau * lambda;
+  b.u = x;
+  for (int t = 1; t <= iters; ++t) {
+    CS_LAUNCH(timed(T_A_ISTA, s, [&] { return launchA(*P, A_ISTA, a, s); }));
+    b.last = (t == iters);
+    CS_LAUNCH(timed(T_B_ISTA, s, [&] { return launchB(*P, B_ISTA, b, s); }));
+  }
+  g_err.clear();
+  return CS_OK;
+}
+
+cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, float lambda,
+                        float rho, int32_t iters, int32_t warm, float* x, float* z, float* u,
+                        float* obj, cs_stream stream) {
+  cs_status st = check_common(c, n, d);
+  if (st != CS_OK) return st;
+  if (!y || !x || !z || !u) return fail(CS_EINVAL, "y, x, z or u is NULL");
+  if (!finite(lambda) || lambda < 0.0f) return fail(CS_EINVAL, "lambda=%g must be finite and >= 0", lambda);
+  if (!finite(rho) || rho <= 0.0f) return fail(CS_EINVAL, "rho=%g must be finite and > 0", rho);
+  if (iters < 0) return fail(CS_EINVAL, "iters=%d must be >= 0", iters);
+  if (obj) return fail(CS_ENOTSUP, "objective trace is not supported; pass obj = NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (iters == 0) {
+    if (!warm) {
+      if ((st = fill(x, size_t(n), 0.0f, s)) != CS_OK) return st;
+      if ((st = fill(z, size_t(n), 0.0f, s)) != CS_OK) return st;
+      if ((st = fill(u, size_t(n), 0.0f, s)) != CS_OK) return st;
+    }
+    g_err.clear();
+    return CS_OK;
+  }
+  Plan* P = nullptr;
+  if ((st = get_plan(n, d, &P)) != CS_OK) return st;
+  if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
+  if ((st = setup_yhat(*P, y, s)) != CS_OK) return st;
+  if (warm) {
+    PassBArgs b0 = argsB(*P);
+    b0.in0 = z;
+    b0.in1 = u;
+    CS_LAUNCH(launchB(*P, B_FWD_ZMU, b0, s));
+  } else {
+    if ((st = fill(reinterpret_cast<float*>(P->Y), size_t(P->N) * 2, 0.0f, s)) != CS_OK) return st;
+    if ((st = fill(u, size_t(n), 0.0f, s)) != CS_OK) return st;
+  }
+  PassAArgs a = argsA(*P);
+  a.rho = rho;
+  a.inv_rho = float(1.0 / double(rho));
+  a.d_rho = float(double(d) * double(rho));
+  PassBArgs b = argsB(*P);
+  b.thr = float(double(lambda) / double(rho));
+  b.out0 = x;
+  b.out1 = z;
+  b.u = u;
+  for (int t = 1; t <= iters; ++t) {
+    CS_LAUNCH(timed(T_A_ADMM, s, [&] { return launchA(*P, A_ADMM, a, s); }));
+    b.last = (t == iters);
+    CS_LAUNCH(timed(T_B_ADMM, s, [&] { return launchB(*P, B_ADMM, b, s); }));
+  }
+  g_err.clear();
+  return CS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1707_02244_amd as cs
+from paper_1707_02244_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "cscirc.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cs_[a-z_A-Z0-9]+)\s*\(", text)))
+
+
+def test_header_declares_expected_calls():
+    syms = declared_symbols()
+    for name in ["cs_circ_apply", "cs_circ_apply_T", "cs_ista_solve", "cs_admm_solve"]:
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol():
+    lib = cs.load()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    assert sorted(_lib.EXPORTS) == declared_symbols()
+
+
+def test_version():
+    assert cs.version() >= 100
+
+
+NULL = ctypes.c_void_p(0)
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every case below fails validation first
+
+
+@pytest.mark.parametrize("n,d", [(0, 4), (100, 4), (128, 4), (1 << 26, 4), (4096, 1), (4096, 3),
+                                 (4096, 32), (4096, 0), (4096, -4)])
+def test_bad_sizes_rejected(n, d):
+    lib = cs.load()
+    st = lib.cs_circ_apply(FAKE, n, d, FAKE, FAKE, NULL)
+    assert st == _lib.CS_EINVAL
+    assert lib.cs_last_error()
+    st = lib.cs_ista_solve(FAKE, n, d, FAKE, 0.1, 0.1, 5, FAKE, NULL, NULL)
+    assert st == _lib.CS_EINVAL
+
+
+def test_null_pointers_rejected():
+    lib = cs.load()
+    assert lib.cs_circ_apply(NULL, 4096, 4, FAKE, FAKE, NULL) == _lib.CS_EINVAL
+    assert lib.cs_circ_apply(FAKE, 4096, 4, NULL, FAKE, NULL) == _lib.CS_EINVAL
+    assert lib.cs_circ_apply_T(FAKE, 4096, 4, FAKE, NULL, NULL) == _lib.CS_EINVAL
+    assert lib.cs_circ_norm_bound(FAKE, 4096, NULL, NULL) == _lib.CS_EINVAL
+    assert lib.cs_ista_solve(FAKE, 4096, 4, NULL, 0.1, 0.1, 5, FAKE, NULL, NULL) == _lib.CS_EINVAL
+    assert lib.cs_admm_solve(FAKE, 4096, 4, FAKE, 0.1, 1.0, 5, 0, FAKE, NULL, FAKE, NULL, NULL) == _lib.CS_EINVAL
+
+
+@pytest.mark.parametrize("lam,tau,iters", [(-1.0, 0.1, 5), (0.1, 0.0, 5), (0.1, -1.0, 5), (0.1, 0.1, -1),
+                                           (float("nan"), 0.1, 5), (0.1, float("inf"), 5)])
+def test_bad_ista_scalars_rejected(lam, tau, iters):
+    lib = cs.load()
+    assert lib.cs_ista_solve(FAKE, 4096, 4, FAKE, lam, tau, iters, FAKE, NULL, NULL) == _lib.CS_EINVAL
+
+
+@pytest.mark.parametrize("lam,rho,iters", [(-1.0, 1.0, 5), (0.1, 0.0, 5), (0.1, -2.0, 5), (0.1, 1.0, -3),
+                                           (0.1, float("nan"), 5)])
+def test_bad_admm_scalars_rejected(lam, rho, iters):
+    lib = cs.load()
+    assert lib.cs_admm_solve(FAKE, 4096, 4, FAKE, lam, rho, iters, 0, FAKE, FAKE, FAKE, NULL, NULL) == _lib.CS_EINVAL
+
+
+def test_objective_trace_not_supported():
+    lib = cs.load()
+    assert lib.cs_ista_solve(FAKE, 4096, 4, FAKE, 0.1, 0.1, 5, FAKE, FAKE, NULL) == _lib.CS_ENOTSUP
+    assert lib.cs_admm_solve(FAKE, 4096, 4, FAKE, 0.1, 1.0, 5, 0, FAKE, FAKE, FAKE, FAKE, NULL) == _lib.CS_ENOTSUP
+
+
+def test_timing_read_unknown_name():
+    lib = cs.load()
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    assert lib.cs_timing_read(b"no_such_kernel", ctypes.byref(n), ctypes.byref(ms)) == _lib.CS_EINVAL
+
+
+def test_package_has_no_oracle_dependency():
+    """The product package never imports the oracle."""
+    pkg = os.path.dirname(cs.__file__)
+    for root, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(root, f)).read()
+                assert "oracle" not in text.lower(), f
