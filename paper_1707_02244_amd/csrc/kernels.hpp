@@ -118,36 +118,101 @@ template <int N2, int OP, int D2>
 __global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
   constexpr int T = kThreads;
   constexpr int LD = N2 + kPadA;
+  constexpr int EPT = (2 * N2 + T - 1) / T;           // row elements per thread
+  constexpr bool GROUP = (OP == A_ISTA || OP == A_ADMM);
+  constexpr int MC = N2 / D2;                         // alias classes per row (= m / N1)
+  constexpr int GPT = GROUP ? (MC + 1 + T - 1) / T : 1;
+  // row-FFT stage twiddles W_{N2}^e: copied to LDS when both rows and the
+  // table fit in the 160 KiB of a CU, read from the global table otherwise
+  constexpr bool TW_LDS = (2 * LD + N2) * 8 <= 160 * 1024 - 1024;
   __shared__ float2 lds[2 * LD];
+  __shared__ float2 tws_l[TW_LDS ? N2 : 1];
+  const float2* tws = TW_LDS ? tws_l : a.tw2;
   const int tid = threadIdx.x;
   const int w = blockIdx.x;
   const int N1 = a.N1;
   const int ra = w;                          // row in slot 0
   const int rb = w ? (N1 - w) : (N1 >> 1);   // row in slot 1
 
-  for (int i = tid; i < 2 * N2; i += T) {
-    const int s = i / N2, p = i % N2;
-    lds[s * LD + p] = a.Y[(size_t)(s ? rb : ra) * N2 + p];
+  // Issue every global load of this workgroup before the first wait: the two
+  // rows, the row-FFT twiddles and (update modes) each class's c_hat, y_hat
+  // and split twiddles.
+  float2 rv[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int i = tid + k * T;
+    if ((2 * N2) % T == 0 || i < 2 * N2) {
+      const int s = i / N2, p = i % N2;
+      rv[k] = a.Y[(size_t)(s ? rb : ra) * N2 + p];
+    }
+  }
+  constexpr int TPT = TW_LDS ? (N2 + T - 1) / T : 1;
+  float2 tv[TPT];
+  if constexpr (TW_LDS) {
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+      const int i = tid + k * T;
+      if (N2 % T == 0 || i < N2) tv[k] = a.tw2[i];
+    }
+  }
+  // class decode: mode 0 = row pair (w > 0); 1 = row 0; 2 = row N1/2 (w = 0)
+  float2 gca[GPT][D2], gcb[GPT][D2], gw[GPT][D2], gy[GPT];
+  const int M = MC;
+  const int ng = w ? M : (M + 1);
+  if constexpr (GROUP) {
+#pragma unroll
+    for (int k = 0; k < GPT; ++k) {
+      const int g = tid + k * T;
+      if (g < ng) {
+        int rowa, k2, mode;
+        if (w) { rowa = w; k2 = g; mode = 0; }
+        else if (g <= (M >> 1)) { rowa = 0; k2 = g; mode = 1; }
+        else { rowa = N1 >> 1; k2 = g - (M >> 1) - 1; mode = 2; }
+        const int rowb = (mode == 0) ? (N1 - w) : rowa;
+        const float2 wk1 = a.twk1[rowa];
+#pragma unroll
+        for (int l = 0; l < D2; ++l) {
+          const int p = k2 + l * M;
+          const int q = (mode == 1) ? ((N2 - p) & (N2 - 1)) : (N2 - 1 - p);
+          gw[k][l] = cmul(wk1, a.twp[p]);
+          gca[k][l] = a.chat[(size_t)rowa * N2 + p];
+          gcb[k][l] = (mode == 1 && p == 0) ? a.chat[a.N] : a.chat[(size_t)rowb * N2 + q];
+        }
+        gy[k] = a.yhat[(size_t)rowa * N2 + k2];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int i = tid + k * T;
+    if ((2 * N2) % T == 0 || i < 2 * N2) lds[(i / N2) * LD + (i % N2)] = rv[k];
+  }
+  if constexpr (TW_LDS) {
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+      const int i = tid + k * T;
+      if (N2 % T == 0 || i < N2) tws_l[i] = tv[k];
+    }
   }
   __syncthreads();
-  lds_fft<N2, 2, T, false, false, LD>(lds, a.tw2, tid);
+  lds_fft<N2, 2, T, false, false, LD>(lds, tws, tid);
 
-  if constexpr (OP == A_ISTA || OP == A_ADMM) {
+  if constexpr (GROUP) {
     // Alias classes.  For w > 0: class k' = w + N1*k2, k2 < M, has a-bins at
     // row w positions k2 + l*M and b-bins at row N1-w positions N2-1-k2-l*M.
     // For w = 0: row 0 classes k2 in [0, M/2] (b positions (N2 - p) mod N2;
     // k2 = 0 and M/2 are their own mirror: write the a side only), then row
     // N1/2 classes k2 in [0, M/2) (b positions N2-1-p in the same row).
-    const int M = a.M;
-    const int ng = w ? M : (M + 1);
-    for (int g = tid; g < ng; g += T) {
-      int sa, sb, rowa, k2, mode;  // mode 0: pair rows, 1: row 0, 2: row N1/2
-      if (w) { sa = 0; sb = 1; rowa = w; k2 = g; mode = 0; }
-      else if (g <= (M >> 1)) { sa = 0; sb = 0; rowa = 0; k2 = g; mode = 1; }
-      else { sa = 1; sb = 1; rowa = N1 >> 1; k2 = g - (M >> 1) - 1; mode = 2; }
-      const int rowb = (mode == 0) ? (N1 - w) : rowa;
+#pragma unroll
+    for (int k = 0; k < GPT; ++k) {
+      const int g = tid + k * T;
+      if (g >= ng) continue;
+      int sa, sb, k2, mode;
+      if (w) { sa = 0; sb = 1; k2 = g; mode = 0; }
+      else if (g <= (M >> 1)) { sa = 0; sb = 0; k2 = g; mode = 1; }
+      else { sa = 1; sb = 1; k2 = g - (M >> 1) - 1; mode = 2; }
       const bool write_b = !(mode == 1 && (k2 == 0 || k2 == (M >> 1)));
-      float2 Xa[D2], Xb[D2], ca[D2], cb[D2], wa[D2];
+      float2 Xa[D2], Xb[D2];
       int pa[D2], qb[D2];
 #pragma unroll
       for (int l = 0; l < D2; ++l) {
@@ -155,51 +220,46 @@ __global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
         const int q = (mode == 1) ? ((N2 - p) & (N2 - 1)) : (N2 - 1 - p);
         pa[l] = p; qb[l] = q;
         const float2 za = lds[sa * LD + p];
-        const float2 zb = lds[sb * LD + q];
-        const float2 wt = cmul(a.twk1[rowa], a.twp[p]);
-        wa[l] = wt;
-        const float2 zbc = cconj(zb);
+        const float2 zbc = cconj(lds[sb * LD + q]);
         const float2 P = cscale(cadd(za, zbc), 0.5f);
         const float2 Q = cscale(cmulmi(csub(za, zbc)), 0.5f);
-        const float2 wq = cmul(wt, Q);
+        const float2 wq = cmul(gw[k][l], Q);
         Xa[l] = cadd(P, wq);
         Xb[l] = cconj(csub(P, wq));
-        ca[l] = a.chat[(size_t)rowa * N2 + p];
-        cb[l] = (mode == 1 && p == 0) ? a.chat[a.N] : a.chat[(size_t)rowb * N2 + q];
       }
-      const float2 yk = a.yhat[(size_t)rowa * N2 + k2];
+      const float2 yk = gy[k];
       float2 Va[D2], Vb[D2];
       if constexpr (OP == A_ISTA) {
         float2 sa_ = c2(0.f, 0.f), sb_ = c2(0.f, 0.f);
 #pragma unroll
-        for (int l = 0; l < D2; ++l) { sa_ = cadd(sa_, cmul(ca[l], Xa[l])); sb_ = cadd(sb_, cmul(cb[l], Xb[l])); }
+        for (int l = 0; l < D2; ++l) { sa_ = cadd(sa_, cmul(gca[k][l], Xa[l])); sb_ = cadd(sb_, cmul(gcb[k][l], Xb[l])); }
         const float2 S = cscale(cadd(sa_, cconj(sb_)), a.inv_d);
         const float2 E = cscale(csub(yk, S), a.tau);
         const float2 Ec = cconj(E);
 #pragma unroll
         for (int l = 0; l < D2; ++l) {
-          Va[l] = cconjmul(ca[l], E);
-          Vb[l] = cconjmul(cb[l], Ec);
+          Va[l] = cconjmul(gca[k][l], E);
+          Vb[l] = cconjmul(gcb[k][l], Ec);
         }
       } else {
         float2 Qa[D2], Qb[D2];
         const float2 ykc = cconj(yk);
         float2 ra_ = c2(0.f, 0.f), rb_ = c2(0.f, 0.f);
-        float lam = a.d_rho;
+        float den = a.d_rho;   // d*rho + sum over the class of |c_hat|^2 = d (rho + Lam)
 #pragma unroll
         for (int l = 0; l < D2; ++l) {
-          Qa[l] = cadd(cconjmul(ca[l], yk), cscale(Xa[l], a.rho));
-          Qb[l] = cadd(cconjmul(cb[l], ykc), cscale(Xb[l], a.rho));
-          ra_ = cadd(ra_, cmul(ca[l], Qa[l]));
-          rb_ = cadd(rb_, cmul(cb[l], Qb[l]));
-          lam += cabs2(ca[l]) + cabs2(cb[l]);
+          Qa[l] = cadd(cconjmul(gca[k][l], yk), cscale(Xa[l], a.rho));
+          Qb[l] = cadd(cconjmul(gcb[k][l], ykc), cscale(Xb[l], a.rho));
+          ra_ = cadd(ra_, cmul(gca[k][l], Qa[l]));
+          rb_ = cadd(rb_, cmul(gcb[k][l], Qb[l]));
+          den += cabs2(gca[k][l]) + cabs2(gcb[k][l]);
         }
-        const float2 Tq = cscale(cadd(ra_, cconj(rb_)), 1.0f / lam);
+        const float2 Tq = cscale(cadd(ra_, cconj(rb_)), 1.0f / den);
         const float2 Tc = cconj(Tq);
 #pragma unroll
         for (int l = 0; l < D2; ++l) {
-          Va[l] = cscale(csub(Qa[l], cconjmul(ca[l], Tq)), a.inv_rho);
-          Vb[l] = cscale(csub(Qb[l], cconjmul(cb[l], Tc)), a.inv_rho);
+          Va[l] = cscale(csub(Qa[l], cconjmul(gca[k][l], Tq)), a.inv_rho);
+          Vb[l] = cscale(csub(Qb[l], cconjmul(gcb[k][l], Tc)), a.inv_rho);
         }
       }
       // inverse split, scaled by 1/n (1/2 of the split times 1/N of the inverse)
@@ -207,7 +267,7 @@ __global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
       for (int l = 0; l < D2; ++l) {
         const float2 vbc = cconj(Vb[l]);
         const float2 E_ = cscale(cadd(Va[l], vbc), a.inv_n);
-        const float2 O_ = cscale(cmulc(csub(Va[l], vbc), wa[l]), a.inv_n);
+        const float2 O_ = cscale(cmulc(csub(Va[l], vbc), gw[k][l]), a.inv_n);
         lds[sa * LD + pa[l]] = cadd(E_, cmuli(O_));
         if (write_b) lds[sb * LD + qb[l]] = cconj(csub(E_, cmuli(O_)));
       }
@@ -255,68 +315,107 @@ __global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
   }
   if constexpr (OP != A_SPEC) {
     __syncthreads();
-    lds_fft<N2, 2, T, true, false, LD>(lds, a.tw2, tid);
-    for (int i = tid; i < 2 * N2; i += T) {
-      const int s = i / N2, p = i % N2;
-      a.Y[(size_t)(s ? rb : ra) * N2 + p] = lds[s * LD + p];
+    lds_fft<N2, 2, T, true, false, LD>(lds, tws, tid);
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int i = tid + k * T;
+      if ((2 * N2) % T == 0 || i < 2 * N2) {
+        const int s = i / N2, p = i % N2;
+        a.Y[(size_t)(s ? rb : ra) * N2 + p] = lds[s * LD + p];
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
 // Pass B.  Workgroup b owns columns j2 in [b*CB, b*CB + CB); LDS holds them
-// interleaved, element (column c, index i) at [i*CB + c].
+// interleaved, element (column c, index i) at [i*CB + c].  Global accesses are
+// issued in register-staged chunks of CH elements per thread so that a chunk's
+// loads are all in flight before the first wait.
 template <int N1, int MODE>
 __global__ __launch_bounds__(kThreads) void k_passB(PassBArgs a) {
   constexpr int T = kThreads;
   constexpr int CB = kColsPerBlock;
   constexpr int NE = N1 * CB;
+  constexpr int EPT = (NE + T - 1) / T;
+  constexpr int CH = EPT < 8 ? EPT : 8;
+  constexpr bool FULL = (NE % T) == 0;
   __shared__ float2 lds[NE];
+  __shared__ float2 tws[N1];
   const int tid = threadIdx.x;
   const int j2_0 = blockIdx.x * CB;
   const int N2 = a.N2;
   constexpr bool HAS_INV = (MODE == B_ISTA || MODE == B_ADMM || MODE == B_OUT_ALL || MODE == B_OUT_DEC);
 
+  {
+    constexpr int TPT = (N1 + T - 1) / T;
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+      const int i = tid + k * T;
+      if (N1 % T == 0 || i < N1) tws[i] = a.tw1[i];
+    }
+  }
   if constexpr (HAS_INV) {
-    for (int i = tid; i < NE; i += T) {
-      const int k1 = i / CB, c = i % CB;
-      const int j2 = j2_0 + c;
-      lds[i] = cmulc(a.Y[(size_t)k1 * N2 + j2], tw_N(a, j2 * k1));
+#pragma unroll
+    for (int k0 = 0; k0 < EPT; k0 += CH) {
+      float2 v[CH], t[CH];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int i = tid + (k0 + k) * T;
+        if (FULL || i < NE) {
+          const int k1 = i / CB, c = i % CB;
+          const int j2 = j2_0 + c;
+          v[k] = a.Y[(size_t)k1 * N2 + j2];
+          t[k] = tw_N(a, j2 * k1);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int i = tid + (k0 + k) * T;
+        if (FULL || i < NE) lds[i] = cmulc(v[k], t[k]);
+      }
     }
     __syncthreads();
-    lds_fft<N1, CB, T, true, true, N1>(lds, a.tw1, tid);
+    lds_fft<N1, CB, T, true, true, N1>(lds, tws, tid);
     // time domain: lds[j1*CB + c] = (x_{2j}, x_{2j+1}), j = N2*j1 + j2_0 + c
     bool fwd = true;
-    if constexpr (MODE == B_ISTA) {
-      // lds holds tau A^T r in the time domain; a.u is the iterate x.
+    if constexpr (MODE == B_ISTA || MODE == B_ADMM) {
+      // ISTA: lds holds tau A^T r and a.u is the iterate x.
+      // ADMM: lds holds x(t) and a.u is the scaled dual u.
       const float thr = a.thr;
-      float2* xs = reinterpret_cast<float2*>(a.u);
-      for (int i = tid; i < NE; i += T) {
-        const int j1 = i / CB, c = i % CB;
-        const size_t j = (size_t)j1 * N2 + j2_0 + c;
-        const float2 v = cadd(xs[j], lds[i]);
-        const float2 x = c2(soft(v.x, thr), soft(v.y, thr));
-        xs[j] = x;
-        lds[i] = x;
-      }
-      fwd = !a.last;
-    } else if constexpr (MODE == B_ADMM) {
-      const float thr = a.thr;
-      float2* u = reinterpret_cast<float2*>(a.u);
-      for (int i = tid; i < NE; i += T) {
-        const int j1 = i / CB, c = i % CB;
-        const size_t j = (size_t)j1 * N2 + j2_0 + c;
-        const float2 x = lds[i];
-        const float2 u0 = u[j];
-        const float2 xu = cadd(x, u0);
-        const float2 z = c2(soft(xu.x, thr), soft(xu.y, thr));
-        const float2 u1 = csub(xu, z);
-        u[j] = u1;
-        if (a.last) {
-          reinterpret_cast<float2*>(a.out0)[j] = x;
-          reinterpret_cast<float2*>(a.out1)[j] = z;
-        } else {
-          lds[i] = csub(z, u1);
+      float2* st = reinterpret_cast<float2*>(a.u);
+#pragma unroll
+      for (int k0 = 0; k0 < EPT; k0 += CH) {
+        float2 sv[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int i = tid + (k0 + k) * T;
+          if (FULL || i < NE) sv[k] = st[(size_t)(i / CB) * N2 + j2_0 + (i % CB)];
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int i = tid + (k0 + k) * T;
+          if (FULL || i < NE) {
+            const size_t j = (size_t)(i / CB) * N2 + j2_0 + (i % CB);
+            if constexpr (MODE == B_ISTA) {
+              const float2 v = cadd(sv[k], lds[i]);
+              const float2 x = c2(soft(v.x, thr), soft(v.y, thr));
+              st[j] = x;
+              lds[i] = x;
+            } else {
+              const float2 x = lds[i];
+              const float2 xu = cadd(x, sv[k]);
+              const float2 z = c2(soft(xu.x, thr), soft(xu.y, thr));
+              const float2 u1 = csub(xu, z);
+              st[j] = u1;
+              if (a.last) {
+                reinterpret_cast<float2*>(a.out0)[j] = x;
+                reinterpret_cast<float2*>(a.out1)[j] = z;
+              } else {
+                lds[i] = csub(z, u1);
+              }
+            }
+          }
         }
       }
       fwd = !a.last;
@@ -339,27 +438,49 @@ __global__ __launch_bounds__(kThreads) void k_passB(PassBArgs a) {
     if (!fwd) return;
     __syncthreads();
   } else {
-    for (int i = tid; i < NE; i += T) {
-      const int j1 = i / CB, c = i % CB;
-      const size_t j = (size_t)j1 * N2 + j2_0 + c;
-      float2 v;
-      if constexpr (MODE == B_FWD_REAL) {
-        v = reinterpret_cast<const float2*>(a.in0)[j];
-      } else if constexpr (MODE == B_FWD_UP) {
-        const int h = a.d >> 1;
-        v = c2((j % h) == 0 ? a.in0[j / h] : 0.0f, 0.0f);
-      } else {
-        v = csub(reinterpret_cast<const float2*>(a.in0)[j], reinterpret_cast<const float2*>(a.in1)[j]);
+#pragma unroll
+    for (int k0 = 0; k0 < EPT; k0 += CH) {
+      float2 v[CH];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int i = tid + (k0 + k) * T;
+        if (FULL || i < NE) {
+          const size_t j = (size_t)(i / CB) * N2 + j2_0 + (i % CB);
+          if constexpr (MODE == B_FWD_REAL) {
+            v[k] = reinterpret_cast<const float2*>(a.in0)[j];
+          } else if constexpr (MODE == B_FWD_UP) {
+            const int h = a.d >> 1;
+            v[k] = c2((j % h) == 0 ? a.in0[j / h] : 0.0f, 0.0f);
+          } else {
+            v[k] = csub(reinterpret_cast<const float2*>(a.in0)[j], reinterpret_cast<const float2*>(a.in1)[j]);
+          }
+        }
       }
-      lds[i] = v;
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int i = tid + (k0 + k) * T;
+        if (FULL || i < NE) lds[i] = v[k];
+      }
     }
     __syncthreads();
   }
-  lds_fft<N1, CB, T, false, true, N1>(lds, a.tw1, tid);
-  for (int i = tid; i < NE; i += T) {
-    const int k1 = i / CB, c = i % CB;
-    const int j2 = j2_0 + c;
-    a.Y[(size_t)k1 * N2 + j2] = cmul(lds[i], tw_N(a, j2 * k1));
+  lds_fft<N1, CB, T, false, true, N1>(lds, tws, tid);
+#pragma unroll
+  for (int k0 = 0; k0 < EPT; k0 += CH) {
+    float2 t[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      const int i = tid + (k0 + k) * T;
+      if (FULL || i < NE) t[k] = tw_N(a, (j2_0 + (i % CB)) * (i / CB));
+    }
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      const int i = tid + (k0 + k) * T;
+      if (FULL || i < NE) {
+        const int k1 = i / CB, c = i % CB;
+        a.Y[(size_t)k1 * N2 + j2_0 + c] = cmul(lds[i], t[k]);
+      }
+    }
   }
 }
 
