@@ -30,17 +30,28 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_bytes(n, d):
-    """Algorithmic HBM bytes per launch of each per-iteration kernel (float32).
+def kernel_bytes(n, d, ista_iters, admm_iters):
+    """Algorithmic bytes per launch of each solver kernel (float32).
 
-    passA (ISTA and ADMM): spectrum Y read + write (2 * 4n), c_hat table read
-    (N + 1 complex = 4n), y_hat read for the m/2 + 1 alias classes (4m).
-    passB_ista: Y read + write and the iterate x read + write (16n).
-    passB_admm: Y read + write and the dual u read + write (16n).
+    Two-launch schedule (per iteration):
+      passA (ISTA and ADMM): spectrum Y read + write (8n), c_hat read (4n),
+        y_hat read for the m/2 + 1 alias classes (4m);
+      passB_ista / passB_admm: Y read + write and the time-domain state
+        (x or u) read + write (16n).
+    Persistent schedule (one launch = a whole solve): per iteration Y is
+      read and written by both passes (16n) and c_hat / y_hat are read
+      (4n + 4m); the state stays in registers.  Bytes per launch = iterations
+      x (20n + 4m), plus the state and outputs moved once.
     """
     m = n // d
     a = 12 * n + 4 * m
-    return {"passA_ista": a, "passB_ista": 16 * n, "passA_admm": a, "passB_admm": 16 * n}
+    per_it = 20 * n + 4 * m
+    return {"passA_ista": a, "passB_ista": 16 * n, "passA_admm": a, "passB_admm": 16 * n,
+            "solve_ista": ista_iters * per_it + 4 * n,
+            "solve_admm": admm_iters * per_it + 12 * n}
+
+
+ITER_BYTES_NOTE = "per iteration: 20n + 4m bytes (persistent) or 28n + 4m (two launches)"
 
 
 def main():
@@ -122,10 +133,7 @@ def main():
         "admm_ms_per_solve": admm_ms,
     }
 
-    # model GB/s for the whole iteration (per-kernel bytes summed)
-    kb = kernel_bytes(n, d)
-    out["ista_model_GBs"] = (kb["passA_ista"] + kb["passB_ista"]) * out["ista_it_s"] / 1e9
-    out["admm_model_GBs"] = (kb["passA_admm"] + kb["passB_admm"]) * out["admm_it_s"] / 1e9
+    kb = kernel_bytes(n, d, T_ista, T_admm)
 
     if not args.no_roofline:
         cs.timing_enable(True)
@@ -135,9 +143,11 @@ def main():
         kern = {}
         for name in kb:
             cnt, tot = cs.timing_read(name)
-            kern[name] = {"launches": cnt, "avg_us": 1e3 * tot / max(cnt, 1), "total_ms": tot,
+            if cnt == 0:
+                continue
+            kern[name] = {"launches": cnt, "avg_us": 1e3 * tot / cnt, "total_ms": tot,
                           "bytes_per_launch": kb[name],
-                          "GBs": kb[name] / (tot / max(cnt, 1) / 1e3) / 1e9 if cnt else None}
+                          "GBs": kb[name] / (tot / cnt / 1e3) / 1e9}
         dom = max(kern, key=lambda k: kern[k]["total_ms"])
         ach = kern[dom]["GBs"]
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
@@ -145,6 +155,8 @@ def main():
                            "avg_launch_us": kern[dom]["avg_us"],
                            "bytes_per_launch": kern[dom]["bytes_per_launch"]}
         out["kernels"] = kern
+        out["bytes_model"] = ITER_BYTES_NOTE
+        cs.check_device()
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sig, prm, tau, lam)

@@ -86,11 +86,25 @@ cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, fl
                         float rho, int32_t iters, int32_t warm, float* x, float* z, float* u,
                         float* obj, cs_stream stream);
 
+/* Solver schedule.  For 2^8 <= n <= 2^22 a solve runs as ONE cooperative
+ * launch: all iterations in a persistent kernel whose workgroups keep the
+ * time-domain state in registers and meet at a grid barrier between the row
+ * and column passes.  Larger n (or path 1) uses two launches per iteration
+ * with the state in HBM.  Both compute the same iterates.  path: 0 = choose
+ * per size (default), 1 = two launches per iteration, 2 = persistent (the
+ * solve returns CS_ENOTSUP where it does not fit).  Process-wide.  */
+cs_status cs_set_solver_path(int32_t path);
+
+/* Synchronise `stream` and report device-side errors of earlier solves on
+ * the current device: CS_EHIP if a persistent solve's grid-barrier wait hit
+ * its bound (its results are then invalid).  Clears the flag.  */
+cs_status cs_check_device(cs_stream stream);
+
 /* Kernel timing (diagnostics, for benchmarks).  While enabled, every launch
- * of the solvers' two per-iteration kernels is bracketed by a pair of
+ * of the solvers' per-iteration kernels (or persistent solve kernel) is bracketed by a pair of
  * hipEvents recorded on the caller's stream.  cs_timing_read waits for the
  * recorded launches of one kernel ("passA_ista", "passB_ista", "passA_admm",
- * "passB_admm"), returns their count and summed duration in milliseconds,
+ * "passB_admm", or the persistent "solve_ista", "solve_admm"), returns their count and summed duration in milliseconds,
  * and forgets them.  Timing adds event records to the stream; leave it off
  * for production runs.  */
 cs_status cs_timing_enable(int32_t on);

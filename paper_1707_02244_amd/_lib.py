@@ -17,7 +17,8 @@ CS_OK, CS_EINVAL, CS_ENOMEM, CS_EHIP, CS_ENOTSUP = 0, -1, -2, -3, -4
 _NAMES = {CS_EINVAL: "CS_EINVAL", CS_ENOMEM: "CS_ENOMEM", CS_EHIP: "CS_EHIP", CS_ENOTSUP: "CS_ENOTSUP"}
 
 EXPORTS = ["cs_circ_apply", "cs_circ_apply_T", "cs_circ_norm_bound", "cs_ista_solve",
-           "cs_admm_solve", "cs_timing_enable", "cs_timing_read", "cs_last_error", "cs_version"]
+           "cs_admm_solve", "cs_set_solver_path", "cs_check_device", "cs_timing_enable",
+           "cs_timing_read", "cs_last_error", "cs_version"]
 
 
 class CsError(RuntimeError):
@@ -45,6 +46,8 @@ def load():
         "cs_circ_norm_bound": [P, I64, P, P],
         "cs_ista_solve": [P, I64, I32, P, F, F, I32, P, P, P],
         "cs_admm_solve": [P, I64, I32, P, F, F, I32, I32, P, P, P, P, P],
+        "cs_set_solver_path": [I32],
+        "cs_check_device": [P],
         "cs_timing_enable": [I32],
         "cs_timing_read": [ctypes.c_char_p, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double)],
         "cs_last_error": [],
@@ -138,6 +141,22 @@ def admm_solve(c, d, y, lam, rho, iters, x=None, z=None, u=None, warm=False, obj
                                 int(iters), int(bool(warm)), _ptr(x, "x", n), _ptr(z, "z", n),
                                 _ptr(u, "u", n), _ptr(obj, "obj", iters), _stream(c)))
     return x, z, u
+
+
+PATH_AUTO, PATH_TWO_PASS, PATH_PERSISTENT = 0, 1, 2
+
+
+def set_solver_path(path):
+    """0: per size (default), 1: two launches per iteration, 2: persistent."""
+    _check(load().cs_set_solver_path(int(path)))
+
+
+def check_device(device=None):
+    """Synchronise the current stream and raise if a persistent solve's grid
+    barrier hit its bound."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+    _check(load().cs_check_device(ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)))
 
 
 def timing_enable(on=True):

@@ -92,24 +92,24 @@ __device__ __forceinline__ void dft(float2* v) {
 }
 
 template <bool ILV, int B, int LD>
-__device__ __forceinline__ int lds_addr(int b, int i) {
+__device__ __forceinline__ unsigned lds_addr(unsigned b, unsigned i) {
   if constexpr (ILV) return i * B + b;
   else return b * LD + i;
 }
 
 template <int L, int B, int T, bool INV, bool ILV, int LD, int NS, int R>
 __device__ __forceinline__ void stockham_stage(float2* __restrict__ buf,
-                                               const float2* __restrict__ tw, int tid) {
+                                               const float2* __restrict__ tw, unsigned tid) {
   constexpr int Q = L / R;          // butterflies per sequence
   constexpr int NBF = B * Q;        // butterflies per stage
   constexpr int PER = (NBF + T - 1) / T;
   float2 v[PER][R];
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
-    const int i = tid + p * T;
+    const unsigned i = tid + p * T;
     if (NBF % T == 0 || i < NBF) {
-      const int b = ILV ? (i % B) : (i / Q);
-      const int j = ILV ? (i / B) : (i % Q);
+      const unsigned b = ILV ? (i % B) : (i / Q);
+      const unsigned j = ILV ? (i / B) : (i % Q);
 #pragma unroll
       for (int r = 0; r < R; ++r) v[p][r] = buf[lds_addr<ILV, B, LD>(b, j + r * Q)];
     }
@@ -117,11 +117,11 @@ __device__ __forceinline__ void stockham_stage(float2* __restrict__ buf,
   __syncthreads();
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
-    const int i = tid + p * T;
+    const unsigned i = tid + p * T;
     if (NBF % T == 0 || i < NBF) {
-      const int b = ILV ? (i % B) : (i / Q);
-      const int j = ILV ? (i / B) : (i % Q);
-      const int k = j & (NS - 1);
+      const unsigned b = ILV ? (i % B) : (i / Q);
+      const unsigned j = ILV ? (i / B) : (i % Q);
+      const unsigned k = j & (NS - 1);
       if constexpr (NS > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -130,7 +130,7 @@ __device__ __forceinline__ void stockham_stage(float2* __restrict__ buf,
         }
       }
       dft<R, INV>(v[p]);
-      const int base = (j - k) * R + k;
+      const unsigned base = (j - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[lds_addr<ILV, B, LD>(b, base + r * NS)] = v[p][r];
     }
@@ -143,7 +143,7 @@ __device__ __forceinline__ void stockham_stage(float2* __restrict__ buf,
 // every stage's stores; the caller barriers before the first call.
 template <int L, int B, int T, bool INV, bool ILV, int LD, int NS = 1>
 __device__ __forceinline__ void lds_fft(float2* __restrict__ buf,
-                                        const float2* __restrict__ tw, int tid) {
+                                        const float2* __restrict__ tw, unsigned tid) {
   if constexpr (NS < L) {
     constexpr int R = stage_radix(L, NS);
     stockham_stage<L, B, T, INV, ILV, LD, NS, R>(buf, tw, tid);

@@ -13,4 +13,11 @@ hipError_t launch_passA(int op, int d2, int grid, const PassAArgs& a, hipStream_
 template <int N1>
 hipError_t launch_passB(int mode, int grid, const PassBArgs& a, hipStream_t s);
 
+struct SolveArgs;
+// persistent solver for N = 2^LOGN complex points (inst_solve.hip)
+template <int LOGN>
+hipError_t launch_solve(int alg, int d2, const SolveArgs& a, hipStream_t s);
+template <int LOGN>
+int solve_blocks_per_cu(int alg, int d2);
+
 }  // namespace cs

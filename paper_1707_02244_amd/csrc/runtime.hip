@@ -21,6 +21,7 @@
 
 #include "../../include/cscirc.h"
 #include "launch.hpp"
+#include "solve_persistent.hpp"
 
 namespace cs {
 namespace {
@@ -47,7 +48,11 @@ cs_status fail(cs_status st, const char* fmt, ...) {
 
 constexpr int64_t kMinN = 256;
 constexpr int64_t kMaxN = int64_t(1) << 25;
-constexpr int kMaxN1 = 2048;
+constexpr int kMinLogNPersistent = 7;    // N = n/2 = 2^7 .. 2^21: one cooperative launch per solve
+constexpr int kMaxLogNPersistent = 21;
+
+// 0: choose per size; 1: two launches per iteration; 2: persistent launch
+int g_path = 0;
 
 int ilog2(int64_t v) {
   int r = 0;
@@ -60,8 +65,10 @@ struct Plan {
   int dev = 0;
   int64_t n = 0;
   int d = 0;
-  int N = 0, N1 = 0, N2 = 0, M = 0, lo_bits = 0;
+  int N = 0, N1 = 0, N2 = 0, M = 0, lo_bits = 0, logN = 0;
+  bool persistent[2][5] = {};   // [alg][d/2 index]: cooperative launch fits
   float2* mem = nullptr;
+  unsigned* bar = nullptr;      // [0] grid barrier counter, [1] error flag
   float2 *Y = nullptr, *chat = nullptr, *yhat = nullptr;
   float2 *tw1 = nullptr, *tw2 = nullptr, *twlo = nullptr, *twhi = nullptr;
   float2 *twk1 = nullptr, *twp = nullptr;
@@ -80,6 +87,26 @@ float2 root(int64_t e, int64_t L) {
   return make_float2(float(std::cos(a)), float(std::sin(a)));
 }
 
+int solve_blocks_per_cu_dispatch(int logN, int alg, int d2) {
+  switch (logN) {
+#define CS_CASE(L) case L: return solve_blocks_per_cu<L>(alg, d2);
+    CS_CASE(7) CS_CASE(8) CS_CASE(9) CS_CASE(10) CS_CASE(11) CS_CASE(12) CS_CASE(13) CS_CASE(14)
+    CS_CASE(15) CS_CASE(16) CS_CASE(17) CS_CASE(18) CS_CASE(19) CS_CASE(20) CS_CASE(21)
+#undef CS_CASE
+    default: return 0;
+  }
+}
+
+hipError_t launch_solve_dispatch(int logN, int alg, int d2, const SolveArgs& a, hipStream_t s) {
+  switch (logN) {
+#define CS_CASE(L) case L: return launch_solve<L>(alg, d2, a, s);
+    CS_CASE(7) CS_CASE(8) CS_CASE(9) CS_CASE(10) CS_CASE(11) CS_CASE(12) CS_CASE(13) CS_CASE(14)
+    CS_CASE(15) CS_CASE(16) CS_CASE(17) CS_CASE(18) CS_CASE(19) CS_CASE(20) CS_CASE(21)
+#undef CS_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
 cs_status get_plan(int64_t n, int d, Plan** out) {
   int dev = 0;
   CS_HIP(hipGetDevice(&dev));
@@ -96,8 +123,10 @@ cs_status get_plan(int64_t n, int d, Plan** out) {
   p->d = d;
   p->N = int(n / 2);
   const int pN = ilog2(p->N);
-  p->N1 = 1 << (pN / 2);
-  if (p->N1 > kMaxN1) p->N1 = kMaxN1;
+  p->logN = pN;
+  // four-step split: odd log2 N -> N2 = 2 N1, even -> N2 = 4 N1 (so the
+  // persistent solver's grid N2/8 owns N1/2 row pairs in 2 or 1 per group)
+  p->N1 = (pN % 2) ? (1 << ((pN - 1) / 2)) : (1 << (pN / 2 - 1));
   p->N2 = p->N / p->N1;
   p->M = int((n / d) / p->N1);
   p->lo_bits = (pN + 1) / 2;
@@ -115,6 +144,19 @@ cs_status get_plan(int64_t n, int d, Plan** out) {
   p->Y = b + oY; p->chat = b + oC; p->yhat = b + oYh;
   p->tw1 = b + oT1; p->tw2 = b + oT2; p->twlo = b + oLo; p->twhi = b + oHi;
   p->twk1 = b + oK1; p->twp = b + oP; p->scal = reinterpret_cast<float*>(b + oS);
+  p->bar = reinterpret_cast<unsigned*>(b + oS) + 16;
+  e = hipMemset(p->bar, 0, 2 * sizeof(unsigned));
+  if (e != hipSuccess) return fail(CS_EHIP, "hipMemset of plan flags failed: %s", hipGetErrorString(e));
+  if (pN >= kMinLogNPersistent && pN <= kMaxLogNPersistent) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
+      for (int alg = 0; alg < 2; ++alg)
+        for (int d2 : {1, 2, 4, 8}) {
+          const int nb = solve_blocks_per_cu_dispatch(pN, alg, d2);
+          p->persistent[alg][ilog2(d2)] = nb >= 1 && int64_t(nb) * cus >= p->N2 / kColsPerBlock;
+        }
+    }
+  }
   std::vector<float2> h(size_t(total - oT1));
   auto put = [&](int64_t off, int64_t cnt, auto fn) {
     for (int64_t i = 0; i < cnt; ++i) h[size_t(off - oT1 + i)] = fn(i);
@@ -189,8 +231,9 @@ hipEvent_t take_event() {
   return e;
 }
 
-enum TimedKind { T_A_ISTA = 0, T_B_ISTA, T_A_ADMM, T_B_ADMM, T_COUNT };
-const char* kTimedNames[T_COUNT] = {"passA_ista", "passB_ista", "passA_admm", "passB_admm"};
+enum TimedKind { T_A_ISTA = 0, T_B_ISTA, T_A_ADMM, T_B_ADMM, T_S_ISTA, T_S_ADMM, T_COUNT };
+const char* kTimedNames[T_COUNT] = {"passA_ista", "passB_ista", "passA_admm", "passB_admm",
+                                    "solve_ista", "solve_admm"};
 
 template <class F>
 hipError_t timed(int kind, hipStream_t s, F&& launch) {
@@ -268,6 +311,26 @@ cs_status fill(float* p, size_t count, float v, hipStream_t s) {
   return CS_OK;
 }
 
+// Whether this solve runs as one cooperative launch.
+cs_status use_persistent(const Plan& P, int alg, bool* out) {
+  const bool fits = P.persistent[alg][ilog2(P.d / 2)];
+  if (g_path == 2 && !fits)
+    return fail(CS_ENOTSUP, "persistent solver not available for n=%lld d=%d", (long long)P.n, P.d);
+  *out = (g_path == 2) || (g_path == 0 && fits);
+  return CS_OK;
+}
+
+SolveArgs solve_args(const Plan& P) {
+  SolveArgs a{};
+  a.Y = P.Y; a.chat = P.chat; a.yhat = P.yhat;
+  a.tw1 = P.tw1; a.tw2 = P.tw2; a.twlo = P.twlo; a.twhi = P.twhi; a.twk1 = P.twk1; a.twp = P.twp;
+  a.lo_bits = P.lo_bits;
+  a.bar = P.bar; a.err = reinterpret_cast<int*>(P.bar + 1);
+  a.inv_n = float(1.0 / double(P.n));
+  a.inv_d = float(1.0 / double(P.d));
+  return a;
+}
+
 __global__ void k_max_abs2(const float2* __restrict__ t, int count, float* __restrict__ out) {
   __shared__ float red[256];
   float m = 0.0f;
@@ -305,6 +368,35 @@ extern "C" {
 const char* cs_last_error(void) { return g_err.c_str(); }
 
 int32_t cs_version(void) { return 100; }
+
+cs_status cs_set_solver_path(int32_t path) {
+  if (path < 0 || path > 2) return fail(CS_EINVAL, "path=%d must be 0, 1 or 2", path);
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_path = path;
+  g_err.clear();
+  return CS_OK;
+}
+
+cs_status cs_check_device(cs_stream stream) {
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  CS_HIP(hipStreamSynchronize(s));
+  int dev = 0;
+  CS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : g_plans) {
+    Plan& P = *kv.second;
+    if (P.dev != dev) continue;
+    unsigned flag = 0;
+    CS_HIP(hipMemcpy(&flag, P.bar + 1, sizeof flag, hipMemcpyDeviceToHost));
+    if (flag) {
+      const unsigned zero = 0;
+      CS_HIP(hipMemcpy(P.bar + 1, &zero, sizeof zero, hipMemcpyHostToDevice));
+      return fail(CS_EHIP, "a grid barrier wait exceeded its bound (n=%lld d=%d)", (long long)P.n, P.d);
+    }
+  }
+  g_err.clear();
+  return CS_OK;
+}
 
 cs_status cs_timing_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_tmu);
@@ -421,6 +513,20 @@ cs_status cs_ista_solve(const float* c, int64_t n, int32_t d, const float* y, fl
   if ((st = get_plan(n, d, &P)) != CS_OK) return st;
   if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
   if ((st = setup_yhat(*P, y, s)) != CS_OK) return st;
+  bool pers = false;
+  if ((st = use_persistent(*P, 0, &pers)) != CS_OK) return st;
+  if (pers) {
+    // counter and error flag start at zero (bit pattern of 0.0f)
+    if ((st = fill(reinterpret_cast<float*>(P->bar), 1, 0.0f, s)) != CS_OK) return st;
+    SolveArgs sa = solve_args(*P);
+    sa.x = x;
+    sa.iters = iters;
+    sa.tau = tau;
+    sa.thr = tau * lambda;
+    CS_LAUNCH(timed(T_S_ISTA, s, [&] { return launch_solve_dispatch(P->logN, 0, d / 2, sa, s); }));
+    g_err.clear();
+    return CS_OK;
+  }
   if ((st = fill(reinterpret_cast<float*>(P->Y), size_t(P->N) * 2, 0.0f, s)) != CS_OK) return st;
   if ((st = fill(x, size_t(n), 0.0f, s)) != CS_OK) return st;
   PassAArgs a = argsA(*P);
@@ -461,6 +567,22 @@ cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, fl
   if ((st = get_plan(n, d, &P)) != CS_OK) return st;
   if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
   if ((st = setup_yhat(*P, y, s)) != CS_OK) return st;
+  bool pers = false;
+  if ((st = use_persistent(*P, 1, &pers)) != CS_OK) return st;
+  if (pers) {
+    if ((st = fill(reinterpret_cast<float*>(P->bar), 1, 0.0f, s)) != CS_OK) return st;
+    SolveArgs sa = solve_args(*P);
+    sa.x = x; sa.z = z; sa.u = u;
+    sa.iters = iters;
+    sa.warm = warm ? 1 : 0;
+    sa.rho = rho;
+    sa.inv_rho = float(1.0 / double(rho));
+    sa.d_rho = float(double(d) * double(rho));
+    sa.thr = float(double(lambda) / double(rho));
+    CS_LAUNCH(timed(T_S_ADMM, s, [&] { return launch_solve_dispatch(P->logN, 1, d / 2, sa, s); }));
+    g_err.clear();
+    return CS_OK;
+  }
   if (warm) {
     PassBArgs b0 = argsB(*P);
     b0.in0 = z;

@@ -27,6 +27,16 @@ IT_TOL = 1e-4
 OBJ_TOL = 1e-5
 
 
+@pytest.fixture(params=["two_pass", "persistent"])
+def path(request):
+    """Run a solver test under both schedules (two launches per iteration, or
+    one persistent cooperative launch), then check the device error flag."""
+    cs.set_solver_path(cs.PATH_TWO_PASS if request.param == "two_pass" else cs.PATH_PERSISTENT)
+    yield request.param
+    cs.check_device()
+    cs.set_solver_path(cs.PATH_AUTO)
+
+
 def g(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
 
@@ -106,7 +116,7 @@ def cfg1():
     return pr, A
 
 
-def test_ista_per_iterate_cfg1(cfg1):
+def test_ista_per_iterate_cfg1(cfg1, path):
     pr, A = cfg1
     y = pr.y.astype(np.float64)
     lam, tau = float(pr.lam), float(pr.tau)
@@ -121,7 +131,7 @@ def test_ista_per_iterate_cfg1(cfg1):
     print("ista cfg1 worst per-iterate rel err (t<=100): %.3e" % worst)
 
 
-def test_ista_final_objective_cfg1(cfg1):
+def test_ista_final_objective_cfg1(cfg1, path):
     pr, A = cfg1
     y = pr.y.astype(np.float64)
     lam, tau = float(pr.lam), float(pr.tau)
@@ -133,7 +143,7 @@ def test_ista_final_objective_cfg1(cfg1):
     assert rel(x, xo) <= IT_TOL
 
 
-def test_admm_per_iterate_cfg1(cfg1):
+def test_admm_per_iterate_cfg1(cfg1, path):
     pr, A = cfg1
     y = pr.y.astype(np.float64)
     lam = float(pr.lam)
@@ -150,7 +160,7 @@ def test_admm_per_iterate_cfg1(cfg1):
     print("admm cfg1 worst per-iterate rel err (t<=100): %.3e" % worst)
 
 
-def test_admm_final_objective_cfg1(cfg1):
+def test_admm_final_objective_cfg1(cfg1, path):
     pr, A = cfg1
     y = pr.y.astype(np.float64)
     lam = float(pr.lam)
@@ -167,7 +177,7 @@ def test_admm_final_objective_cfg1(cfg1):
 # Other decimations and sizes (dense oracle), ADMM with rho != 1
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("n,d,k", [(256, 2, 4), (512, 16, 3), (2048, 8, 12), (8192, 4, 60)])
-def test_solvers_other_shapes(n, d, k):
+def test_solvers_other_shapes(n, d, k, path):
     pr = problem.build(workloads.signal(n, d, k, 100 + n + d))
     A = pr.A()
     y = pr.y.astype(np.float64)
@@ -186,7 +196,7 @@ def test_solvers_other_shapes(n, d, k):
 # ----------------------------------------------------------------------------
 # Degenerate and edge cases
 # ----------------------------------------------------------------------------
-def test_zero_iterations():
+def test_zero_iterations(path):
     n, d = 4096, 4
     c = g(np.ones(n))
     y = g(np.ones(n // d))
@@ -201,7 +211,7 @@ def test_zero_iterations():
     assert np.all(h(z) == 4.0) and np.all(h(u) == 5.0)
 
 
-def test_lambda_at_lam_max_gives_zero(cfg1):
+def test_lambda_at_lam_max_gives_zero(cfg1, path):
     pr, A = cfg1
     lmax = problem.lam_max(pr.c, pr.d, pr.y)
     lam = np.float32(lmax * 1.001)
@@ -209,7 +219,7 @@ def test_lambda_at_lam_max_gives_zero(cfg1):
     assert np.count_nonzero(x) == 0
 
 
-def test_lambda_zero_is_least_squares_gradient(cfg1):
+def test_lambda_zero_is_least_squares_gradient(cfg1, path):
     """lam = 0: one ISTA step from 0 is tau A^T y exactly (no threshold)."""
     pr, A = cfg1
     x = h(cs.ista_solve(g(pr.c), pr.d, g(pr.y), 0.0, pr.tau, 1))
@@ -217,7 +227,7 @@ def test_lambda_zero_is_least_squares_gradient(cfg1):
     check_elementwise(x, ref)
 
 
-def test_admm_warm_start_continues(cfg1):
+def test_admm_warm_start_continues(cfg1, path):
     pr, A = cfg1
     c, yg = g(pr.c), g(pr.y)
     x20, z20, u20 = (h(v) for v in cs.admm_solve(c, pr.d, yg, pr.lam, 1.0, 20))
@@ -226,7 +236,7 @@ def test_admm_warm_start_continues(cfg1):
     assert rel(h(z), z20) <= 1e-6 and rel(h(u), u20) <= 1e-6 and rel(h(x), x20) <= 1e-6
 
 
-def test_deterministic(cfg1):
+def test_deterministic(cfg1, path):
     pr, A = cfg1
     c, yg = g(pr.c), g(pr.y)
     a = h(cs.ista_solve(c, pr.d, yg, pr.lam, pr.tau, 50))
@@ -257,7 +267,7 @@ def cfg2():
     return pr, pr.op()
 
 
-def test_cfg2_ista_first_iterates(cfg2):
+def test_cfg2_ista_first_iterates(cfg2, path):
     pr, op = cfg2
     y = pr.y.astype(np.float64)
     lam, tau = float(pr.lam), float(pr.tau)
@@ -268,7 +278,7 @@ def test_cfg2_ista_first_iterates(cfg2):
         assert rel(x, hist[t - 1][1]) <= IT_TOL, t
 
 
-def test_cfg2_admm_first_iterates(cfg2):
+def test_cfg2_admm_first_iterates(cfg2, path):
     pr, op = cfg2
     y = pr.y.astype(np.float64)
     lam = float(pr.lam)
@@ -285,7 +295,7 @@ def test_cfg2_operator_full_size(cfg2):
     check_elementwise(y, pr.y.astype(np.float64), tol=OP_TOL)
 
 
-def test_cfg2_full_run_objective_decreases(cfg2):
+def test_cfg2_full_run_objective_decreases(cfg2, path):
     """At the benchmark's iteration counts the oracle cannot follow every
     iterate; the GPU iterates must still drive the FP64 objective down
     monotonically (ISTA with tau <= 1/||A||^2 cannot increase it)."""
@@ -300,3 +310,20 @@ def test_cfg2_full_run_objective_decreases(cfg2):
     x, z, u = cs.admm_solve(c, pr.d, yg, pr.lam, 1.0, workloads.CFG2_PARAMS["admm_iters"])
     fz = fftref.objective(op, y, lam, h(z))
     assert fz < f[1]
+
+
+def test_paths_agree(cfg1):
+    """The persistent launch and the two-launch schedule run the same
+    arithmetic in the same order: their iterates agree to FP32 round-off."""
+    pr, A = cfg1
+    c, yg = g(pr.c), g(pr.y)
+    out = {}
+    for p in (cs.PATH_TWO_PASS, cs.PATH_PERSISTENT):
+        cs.set_solver_path(p)
+        out[p] = (h(cs.ista_solve(c, pr.d, yg, pr.lam, pr.tau, 60)),
+                  [h(v) for v in cs.admm_solve(c, pr.d, yg, pr.lam, 1.0, 40)])
+    cs.check_device()
+    cs.set_solver_path(cs.PATH_AUTO)
+    a, b = out[cs.PATH_TWO_PASS], out[cs.PATH_PERSISTENT]
+    assert rel(b[0], a[0]) <= 1e-6
+    assert all(rel(q, p) <= 1e-6 for p, q in zip(a[1], b[1]))
