@@ -1,5 +1,5 @@
-// Workgroup-wide complex FFTs held in LDS: Stockham autosort, radix 8 with one
-// radix-4 (or radix-2) stage where log2(L) is not a multiple of three.
+// Workgroup-wide complex FFTs held in LDS: Stockham autosort with radix-16
+// stages and one radix-2/4/8 stage for the remaining factor.
 //
 // Algorithm: the self-sorting Stockham formulation (C. Van Loan, Computational
 // Frameworks for the Fast Fourier Transform, SIAM 1992, Section 1.7).  Stage s
@@ -14,7 +14,9 @@
 //                columns; consecutive threads take consecutive b so every
 //                LDS access of a stage is unit-stride across the wave)
 // Each stage loads its butterflies into registers, barriers, then stores in
-// place, so LDS holds one copy of the data.  Twiddles come from a table
+// place, so LDS holds one copy of the data.  LDS addresses are padded by one
+// slot per 16 (flat index x lives at x + x/16): with that skew the strided
+// stores of the early radix-16 stages hit distinct banks.  Twiddles come from a table
 // tw[e] = exp(-2 pi i e / L), e < L, computed on the host in double precision.
 // Forward transforms use exp(-...), inverse ones exp(+...), both unnormalised.
 #pragma once
@@ -24,10 +26,32 @@ namespace cs {
 
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 
+#ifndef CS_MAX_RADIX
+#define CS_MAX_RADIX 8
+#endif
+
+// Radix of the stage that starts at span NS.
+// Radix-16 plan: 16 while at least 16 remains; a leftover factor of 2 is
+// avoided by ending with 8 * 4.  Radix-8 plan: radix 8, with one radix-4 (or
+// radix-2) stage first where log2(L) is not a multiple of three.
 constexpr int stage_radix(int L, int NS) {
   const int p = ilog2c(L / NS);
+  if (CS_MAX_RADIX >= 16) {
+    if (p >= 4 && p != 5) return 16;
+    if (p == 5) return 8;
+    return 1 << p;
+  }
   return (p % 3 == 0) ? 8 : ((p % 3 == 2) ? 4 : (p == 1 ? 2 : 4));
 }
+
+#ifndef CS_LDS_PAD
+#define CS_LDS_PAD 0
+#endif
+// LDS slot of flat index x: with CS_LDS_PAD, one padding slot per 16 (skews
+// the strided stores of early stages across banks, at the price of address
+// arithmetic the compiler cannot fold into instruction offsets)
+__device__ __forceinline__ unsigned lp(unsigned x) { return CS_LDS_PAD ? x + (x >> 4) : x; }
+constexpr int lds_padded(int n) { return CS_LDS_PAD ? n + n / 16 + 1 : n; }
 
 // multiply by the primitive 8th root of unity W8^q (q = 1, 3), forward sign
 // exp(-i pi q / 4) or inverse sign exp(+i pi q / 4).
@@ -84,17 +108,54 @@ __device__ __forceinline__ void dft8(float2* v) {
   v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
 }
 
+// 16-point DFT as 4 x 4: with r = 4a + b and k = c + 4d,
+// W16^{rk} = W4^{ac} W16^{bc} W4^{bd}: DFT4 over a for each b, twiddle by
+// W16^{bc}, DFT4 over b for each c.
+template <bool INV>
+__device__ __forceinline__ void dft16(float2* v) {
+  const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;  // cos, sin of pi/8
+  // step 1: t[b][c] in place at v[4c + b]... computed per b over a
+#pragma unroll
+  for (int b = 0; b < 4; ++b) dft4<INV>(v[b], v[4 + b], v[8 + b], v[12 + b]);
+  // now v[4c + b] = t[b][c]; step 2: twiddle W16^{bc} (conjugated for INV)
+  auto tw = [&](float2 a, float cr, float ci) {   // a * (cr + i ci) with ci sign per direction
+    const float si = INV ? -ci : ci;
+    return c2(fmaf(a.x, cr, -a.y * si), fmaf(a.x, si, a.y * cr));
+  };
+  // W16^1 = (c1, -s1), W16^2 = W8^1, W16^3 = (s1, -c1), W16^4 = -i, W16^6 = W8^3, W16^9 = (-c1, s1)
+  v[4 + 1] = tw(v[4 + 1], c1, -s1);          // b=1, c=1
+  v[8 + 1] = mul_w8_1<INV>(v[8 + 1]);        // b=1, c=2
+  v[12 + 1] = tw(v[12 + 1], s1, -c1);        // b=1, c=3
+  v[4 + 2] = mul_w8_1<INV>(v[4 + 2]);        // b=2, c=1
+  v[8 + 2] = mul_w4<INV>(v[8 + 2]);          // b=2, c=2
+  v[12 + 2] = mul_w8_3<INV>(v[12 + 2]);      // b=2, c=3
+  v[4 + 3] = tw(v[4 + 3], s1, -c1);          // b=3, c=1
+  v[8 + 3] = mul_w8_3<INV>(v[8 + 3]);        // b=3, c=2
+  v[12 + 3] = tw(v[12 + 3], -c1, s1);        // b=3, c=3
+  // step 3: for each c, DFT4 over b: y[c + 4d] = sum_b t[b][c] W4^{bd}
+  float2 y[16];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    float2 a0 = v[4 * c], a1 = v[4 * c + 1], a2 = v[4 * c + 2], a3 = v[4 * c + 3];
+    dft4<INV>(a0, a1, a2, a3);
+    y[c] = a0; y[c + 4] = a1; y[c + 8] = a2; y[c + 12] = a3;
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = y[k];
+}
+
 template <int R, bool INV>
 __device__ __forceinline__ void dft(float2* v) {
   if constexpr (R == 2) dft2<INV>(v);
   else if constexpr (R == 4) dft4<INV>(v[0], v[1], v[2], v[3]);
-  else dft8<INV>(v);
+  else if constexpr (R == 8) dft8<INV>(v);
+  else dft16<INV>(v);
 }
 
 template <bool ILV, int B, int LD>
 __device__ __forceinline__ unsigned lds_addr(unsigned b, unsigned i) {
-  if constexpr (ILV) return i * B + b;
-  else return b * LD + i;
+  if constexpr (ILV) return lp(i * B + b);
+  else return lp(b * LD + i);
 }
 
 template <int L, int B, int T, bool INV, bool ILV, int LD, int NS, int R>

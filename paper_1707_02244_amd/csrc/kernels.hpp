@@ -124,8 +124,8 @@ __global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
   constexpr int GPT = GROUP ? (MC + 1 + T - 1) / T : 1;
   // row-FFT stage twiddles W_{N2}^e: copied to LDS when both rows and the
   // table fit in the 160 KiB of a CU, read from the global table otherwise
-  constexpr bool TW_LDS = (2 * LD + N2) * 8 <= 160 * 1024 - 1024;
-  __shared__ float2 lds[2 * LD];
+  constexpr bool TW_LDS = (lds_padded(2 * LD) + N2) * 8 <= 160 * 1024 - 1024;
+  __shared__ float2 lds[lds_padded(2 * LD)];
   __shared__ float2 tws_l[TW_LDS ? N2 : 1];
   const float2* tws = TW_LDS ? tws_l : a.tw2;
   const int tid = threadIdx.x;
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const int i = tid + k * T;
-    if ((2 * N2) % T == 0 || i < 2 * N2) lds[(i / N2) * LD + (i % N2)] = rv[k];
+    if ((2 * N2) % T == 0 || i < 2 * N2) lds[lp((i / N2) * LD + (i % N2))] = rv[k];
   }
   if constexpr (TW_LDS) {
 #pragma unroll
@@ -219,8 +219,8 @@ __global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
         const int p = k2 + l * M;
         const int q = (mode == 1) ? ((N2 - p) & (N2 - 1)) : (N2 - 1 - p);
         pa[l] = p; qb[l] = q;
-        const float2 za = lds[sa * LD + p];
-        const float2 zbc = cconj(lds[sb * LD + q]);
+        const float2 za = lds[lp(sa * LD + p)];
+        const float2 zbc = cconj(lds[lp(sb * LD + q)]);
         const float2 P = cscale(cadd(za, zbc), 0.5f);
         const float2 Q = cscale(cmulmi(csub(za, zbc)), 0.5f);
         const float2 wq = cmul(gw[k][l], Q);
@@ -268,8 +268,8 @@ __global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
         const float2 vbc = cconj(Vb[l]);
         const float2 E_ = cscale(cadd(Va[l], vbc), a.inv_n);
         const float2 O_ = cscale(cmulc(csub(Va[l], vbc), gw[k][l]), a.inv_n);
-        lds[sa * LD + pa[l]] = cadd(E_, cmuli(O_));
-        if (write_b) lds[sb * LD + qb[l]] = cconj(csub(E_, cmuli(O_)));
+        lds[lp(sa * LD + pa[l])] = cadd(E_, cmuli(O_));
+        if (write_b) lds[lp(sb * LD + qb[l])] = cconj(csub(E_, cmuli(O_)));
       }
     }
   } else {
@@ -286,8 +286,8 @@ __global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
       const int rowb = (mode == 0) ? (N1 - w) : rowa;
       const int q = (mode == 1) ? ((N2 - p) & (N2 - 1)) : (N2 - 1 - p);
       const bool write_b = !(mode == 1 && (p == 0 || p == (N2 >> 1)));
-      const float2 za = lds[sa * LD + p];
-      const float2 zb = lds[sb * LD + q];
+      const float2 za = lds[lp(sa * LD + p)];
+      const float2 zb = lds[lp(sb * LD + q)];
       const float2 wt = cmul(a.twk1[rowa], a.twp[p]);
       const float2 zbc = cconj(zb);
       const float2 P = cscale(cadd(za, zbc), 0.5f);
@@ -308,8 +308,8 @@ __global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
         const float2 vbc = cconj(Vb);
         const float2 E_ = cscale(cadd(Va, vbc), a.inv_n);
         const float2 O_ = cscale(cmulc(csub(Va, vbc), wt), a.inv_n);
-        lds[sa * LD + p] = cadd(E_, cmuli(O_));
-        if (write_b) lds[sb * LD + q] = cconj(csub(E_, cmuli(O_)));
+        lds[lp(sa * LD + p)] = cadd(E_, cmuli(O_));
+        if (write_b) lds[lp(sb * LD + q)] = cconj(csub(E_, cmuli(O_)));
       }
     }
   }
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
       const int i = tid + k * T;
       if ((2 * N2) % T == 0 || i < 2 * N2) {
         const int s = i / N2, p = i % N2;
-        a.Y[(size_t)(s ? rb : ra) * N2 + p] = lds[s * LD + p];
+        a.Y[(size_t)(s ? rb : ra) * N2 + p] = lds[lp(s * LD + p)];
       }
     }
   }
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(kThreads) void k_passB(PassBArgs a) {
   constexpr int EPT = (NE + T - 1) / T;
   constexpr int CH = EPT < 8 ? EPT : 8;
   constexpr bool FULL = (NE % T) == 0;
-  __shared__ float2 lds[NE];
+  __shared__ float2 lds[lds_padded(NE)];
   __shared__ float2 tws[N1];
   const int tid = threadIdx.x;
   const int j2_0 = blockIdx.x * CB;
@@ -372,12 +372,12 @@ __global__ __launch_bounds__(kThreads) void k_passB(PassBArgs a) {
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const int i = tid + (k0 + k) * T;
-        if (FULL || i < NE) lds[i] = cmulc(v[k], t[k]);
+        if (FULL || i < NE) lds[lp(i)] = cmulc(v[k], t[k]);
       }
     }
     __syncthreads();
     lds_fft<N1, CB, T, true, true, N1>(lds, tws, tid);
-    // time domain: lds[j1*CB + c] = (x_{2j}, x_{2j+1}), j = N2*j1 + j2_0 + c
+    // time domain: lds[lp(j1*CB + c)] = (x_{2j}, x_{2j+1}), j = N2*j1 + j2_0 + c
     bool fwd = true;
     if constexpr (MODE == B_ISTA || MODE == B_ADMM) {
       // ISTA: lds holds tau A^T r and a.u is the iterate x.
@@ -398,12 +398,12 @@ __global__ __launch_bounds__(kThreads) void k_passB(PassBArgs a) {
           if (FULL || i < NE) {
             const size_t j = (size_t)(i / CB) * N2 + j2_0 + (i % CB);
             if constexpr (MODE == B_ISTA) {
-              const float2 v = cadd(sv[k], lds[i]);
+              const float2 v = cadd(sv[k], lds[lp(i)]);
               const float2 x = c2(soft(v.x, thr), soft(v.y, thr));
               st[j] = x;
-              lds[i] = x;
+              lds[lp(i)] = x;
             } else {
-              const float2 x = lds[i];
+              const float2 x = lds[lp(i)];
               const float2 xu = cadd(x, sv[k]);
               const float2 z = c2(soft(xu.x, thr), soft(xu.y, thr));
               const float2 u1 = csub(xu, z);
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(kThreads) void k_passB(PassBArgs a) {
                 reinterpret_cast<float2*>(a.out0)[j] = x;
                 reinterpret_cast<float2*>(a.out1)[j] = z;
               } else {
-                lds[i] = csub(z, u1);
+                lds[lp(i)] = csub(z, u1);
               }
             }
           }
@@ -423,7 +423,7 @@ __global__ __launch_bounds__(kThreads) void k_passB(PassBArgs a) {
       for (int i = tid; i < NE; i += T) {
         const int j1 = i / CB, c = i % CB;
         const size_t j = (size_t)j1 * N2 + j2_0 + c;
-        reinterpret_cast<float2*>(a.out0)[j] = lds[i];
+        reinterpret_cast<float2*>(a.out0)[j] = lds[lp(i)];
       }
       fwd = false;
     } else {  // B_OUT_DEC: real sample 2j is kept when 2j % d == 0 (d even)
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(kThreads) void k_passB(PassBArgs a) {
       for (int i = tid; i < NE; i += T) {
         const int j1 = i / CB, c = i % CB;
         const size_t j = (size_t)j1 * N2 + j2_0 + c;
-        if ((j % h) == 0) a.out0[j / h] = lds[i].x;
+        if ((j % h) == 0) a.out0[j / h] = lds[lp(i)].x;
       }
       fwd = false;
     }
@@ -459,7 +459,7 @@ __global__ __launch_bounds__(kThreads) void k_passB(PassBArgs a) {
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const int i = tid + (k0 + k) * T;
-        if (FULL || i < NE) lds[i] = v[k];
+        if (FULL || i < NE) lds[lp(i)] = v[k];
       }
     }
     __syncthreads();
@@ -478,7 +478,7 @@ __global__ __launch_bounds__(kThreads) void k_passB(PassBArgs a) {
       const int i = tid + (k0 + k) * T;
       if (FULL || i < NE) {
         const int k1 = i / CB, c = i % CB;
-        a.Y[(size_t)k1 * N2 + j2_0 + c] = cmul(lds[i], t[k]);
+        a.Y[(size_t)k1 * N2 + j2_0 + c] = cmul(lds[lp(i)], t[k]);
       }
     }
   }

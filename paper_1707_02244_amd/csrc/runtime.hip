@@ -19,7 +19,7 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/cscirc.h"
+#include "cscirc.h"
 #include "launch.hpp"
 #include "solve_persistent.hpp"
 

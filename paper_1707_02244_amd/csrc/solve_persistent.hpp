@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
   constexpr bool FB = NEB % T == 0;
   constexpr int M = N2 / D2;                 // alias classes per row (m / N1)
   constexpr int GPT = (AI * M + 1 + T - 1) / T;
-  __shared__ float2 lds[NL];
+  __shared__ float2 lds[lds_padded(NL)];
   __shared__ float2 t1[N1];
   __shared__ float2 t2[N2];
   __shared__ float2 tp[N2];                  // W_{2 N2}^p (real-split twiddle, row part)
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
 #pragma unroll
     for (int k = 0; k < EB; ++k) {
       const unsigned e = tid + k * T;
-      if (FB || e < NEB) st_coh(&Yg[col_index(e)], cmul(lds[e], twb(e)));
+      if (FB || e < NEB) st_coh(&Yg[col_index(e)], cmul(lds[lp(e)], twb(e)));
     }
   };
 
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
       if (FB || e < NEB) {
         const unsigned j = col_index(e);
         st[k] = u2[j];
-        lds[e] = csub(z2[j], st[k]);
+        lds[lp(e)] = csub(z2[j], st[k]);
       }
     }
     __syncthreads();
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
 #pragma unroll
       for (int k = 0; k < EA; ++k) {
         const unsigned i = tid + k * T;
-        if (FA || i < RA * N2) lds[(i / N2) * LDA + (i % N2)] = rv[k];
+        if (FA || i < RA * N2) lds[lp((i / N2) * LDA + (i % N2))] = rv[k];
       }
     }
     __syncthreads();
@@ -252,8 +252,8 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
         const int p = k2 + l * M;
         const int qq = (mode == 1) ? ((N2 - p) & (N2 - 1)) : (N2 - 1 - p);
         gw[l] = cmul(wk1, tp[p]);
-        const float2 za = lds[sa * LDA + p];
-        const float2 zbc = cconj(lds[sb * LDA + qq]);
+        const float2 za = lds[lp(sa * LDA + p)];
+        const float2 zbc = cconj(lds[lp(sb * LDA + qq)]);
         const float2 P = cscale(cadd(za, zbc), 0.5f);
         const float2 Q = cscale(cmulmi(csub(za, zbc)), 0.5f);
         const float2 wq = cmul(gw[l], Q);
@@ -301,8 +301,8 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
         const float2 vbc = cconj(Vb[l]);
         const float2 E_ = cscale(cadd(Va[l], vbc), a.inv_n);
         const float2 O_ = cscale(cmulc(csub(Va[l], vbc), gw[l]), a.inv_n);
-        lds[sa * LDA + p] = cadd(E_, cmuli(O_));
-        if (write_b) lds[sb * LDA + qq] = cconj(csub(E_, cmuli(O_)));
+        lds[lp(sa * LDA + p)] = cadd(E_, cmuli(O_));
+        if (write_b) lds[lp(sb * LDA + qq)] = cconj(csub(E_, cmuli(O_)));
       }
     }
     __syncthreads();
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
         const unsigned s = i / N2, p = i % N2;
         const unsigned w = g + (s >> 1) * G;
         const unsigned row = (s & 1) ? (w ? N1 - w : (N1 >> 1)) : w;
-        st_coh(&Yg[(unsigned)row * N2 + p], lds[s * LDA + p]);
+        st_coh(&Yg[(unsigned)row * N2 + p], lds[lp(s * LDA + p)]);
       }
     }
     grid_barrier(a.bar, (++nbar) * G, a.err);
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
 #pragma unroll
       for (int k = 0; k < EB; ++k) {
           const unsigned e = tid + k * T;
-        if (FB || e < NEB) lds[e] = cmulc(cv[k], twb(e));
+        if (FB || e < NEB) lds[lp(e)] = cmulc(cv[k], twb(e));
       }
     }
     __syncthreads();
@@ -342,12 +342,12 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
       const unsigned e = tid + k * T;
       if (FB || e < NEB) {
         if constexpr (ALG == 0) {
-          const float2 v = cadd(st[k], lds[e]);
+          const float2 v = cadd(st[k], lds[lp(e)]);
           const float2 xv = c2(soft(v.x, thr), soft(v.y, thr));
           st[k] = xv;
-          lds[e] = xv;
+          lds[lp(e)] = xv;
         } else {
-          const float2 xv = lds[e];
+          const float2 xv = lds[lp(e)];
           const float2 xu = cadd(xv, st[k]);
           const float2 zv = c2(soft(xu.x, thr), soft(xu.y, thr));
           const float2 u1 = csub(xu, zv);
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
             reinterpret_cast<float2*>(a.x)[j] = xv;
             reinterpret_cast<float2*>(a.z)[j] = zv;
           } else {
-            lds[e] = csub(zv, u1);
+            lds[lp(e)] = csub(zv, u1);
           }
         }
       }
