@@ -61,6 +61,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the solver path is single-GPU "
@@ -158,9 +159,60 @@ def main():
         out["bytes_model"] = ITER_BYTES_NOTE
         cs.check_device()
 
+    if not args.no_batched:
+        out["batched"] = bench_batched(cs, torch, dev, args.steps, args.warmup)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sig, prm, tau, lam)
     print(json.dumps(out))
+
+
+def bench_batched(cs, torch, dev, steps, warmup):
+    """512 signals, n_i = 2^12 .. 2^18 drawn uniformly in the exponent, d = 4,
+    k_i = n_i/256, per-signal lam and tau, ISTA 200 iterations, one launch.
+    Inputs (y, tau, lam) computed with the library's operators."""
+    import numpy as np
+    import workloads
+    sigs = workloads.cfg4()
+    iters = workloads.CFG4_PARAMS["ista_iters"]
+    d = 4
+    ns = np.array([s.n for s in sigs], dtype=np.int64)
+    c_cat = torch.from_numpy(np.concatenate([s.c for s in sigs])).to(dev)
+    x_true = torch.from_numpy(np.concatenate([s.x_true for s in sigs])).to(dev)
+    off_n, off_m = cs.batch_offsets(ns, d)
+    y_cat = torch.empty(int((ns // d).sum()), device=dev)
+    lam = torch.empty(len(sigs), device=dev)
+    tau = torch.empty(len(sigs), device=dev)
+    for i, n in enumerate(ns):
+        n = int(n)
+        ci = c_cat[off_n[i]:off_n[i] + n]
+        yi = y_cat[off_m[i]:off_m[i] + n // d]
+        cs.circ_apply(ci, d, x_true[off_n[i]:off_n[i] + n], yi)
+        tau[i] = 1.0 / cs.circ_norm_bound(ci)[0]
+        lam[i] = workloads.CFG4_PARAMS["lam_frac"] * cs.circ_apply_T(ci, d, yi).abs().max()
+    x_cat = torch.empty_like(c_cat)
+    run = lambda: cs.ista_solve_batched(ns, d, c_cat, y_cat, lam, tau, iters, x_cat)
+    for _ in range(max(1, warmup)):
+        run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    cs.check_device()
+    sum_n = int(ns.sum())
+    # per signal and iteration: row pass 12n + 4m, column pass 16n (the
+    # iterate lives in the output slice)
+    bytes_it = int(sum(28 * int(n) + 4 * int(n) // d for n in ns))
+    return {"workload": "512 signals, n_i = 2^12..2^18 (uniform exponent), d=4, k_i=n_i/256, ISTA 200 it",
+            "signals": len(sigs), "sum_n": sum_n, "iters": iters, "ms_per_solve": ms,
+            "signals_per_s": len(sigs) / (ms / 1e3),
+            "signal_iterations_per_s": len(sigs) * iters / (ms / 1e3),
+            "model_GBs": bytes_it * iters / (ms / 1e3) / 1e9,
+            "equiv_n2e22_it_s": sum_n * iters / (1 << 22) / (ms / 1e3)}
 
 
 def cpu_baseline(sig, prm, tau, lam):

@@ -86,6 +86,24 @@ cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, fl
                         float rho, int32_t iters, int32_t warm, float* x, float* z, float* u,
                         float* obj, cs_stream stream);
 
+/* Batched ISTA (Alg. 1) over `count` independent signals of different
+ * lengths, in one launch.  Signal i has length n_host[i] (a power of two in
+ * [2^10, 2^18]), its own generator c_cat[off_n_host[i] .. + n), measurements
+ * y_cat[off_m_host[i] .. + n/d), threshold parameters lambda_dev[i] and
+ * tau_dev[i] (device arrays of `count` floats) and output / iterate
+ * x_cat[off_n_host[i] .. + n); d (2, 4 or 8) is shared.  n_host and the
+ * offsets are HOST arrays; off_n must be even.  Output slices must not
+ * overlap.  Each signal is solved exactly as cs_ista_solve would (same
+ * arithmetic), from x(0) = 0, for `iters` iterations.  Workgroups take whole
+ * signals from a work queue, longest first; the launch is one kernel and can
+ * be captured in a HIP graph.  A per-device scratch area (about 3n complex
+ * per signal) is allocated on first use and grown when a larger batch comes;
+ * batched calls on one device must be serialised.  */
+cs_status cs_ista_solve_batched(int32_t count, const int64_t* n_host, int32_t d, const int64_t* off_n_host,
+                                const int64_t* off_m_host, const float* c_cat, const float* y_cat,
+                                const float* lambda_dev, const float* tau_dev, int32_t iters, float* x_cat,
+                                cs_stream stream);
+
 /* Solver schedule.  For 2^8 <= n <= 2^22 a solve runs as ONE cooperative
  * launch: all iterations in a persistent kernel whose workgroups keep the
  * time-domain state in registers and meet at a grid barrier between the row
@@ -104,7 +122,8 @@ cs_status cs_check_device(cs_stream stream);
  * of the solvers' per-iteration kernels (or persistent solve kernel) is bracketed by a pair of
  * hipEvents recorded on the caller's stream.  cs_timing_read waits for the
  * recorded launches of one kernel ("passA_ista", "passB_ista", "passA_admm",
- * "passB_admm", or the persistent "solve_ista", "solve_admm"), returns their count and summed duration in milliseconds,
+ * "passB_admm", the persistent "solve_ista", "solve_admm", or the batched
+ * "batch_ista"), returns their count and summed duration in milliseconds,
  * and forgets them.  Timing adds event records to the stream; leave it off
  * for production runs.  */
 cs_status cs_timing_enable(int32_t on);

@@ -17,7 +17,7 @@ CS_OK, CS_EINVAL, CS_ENOMEM, CS_EHIP, CS_ENOTSUP = 0, -1, -2, -3, -4
 _NAMES = {CS_EINVAL: "CS_EINVAL", CS_ENOMEM: "CS_ENOMEM", CS_EHIP: "CS_EHIP", CS_ENOTSUP: "CS_ENOTSUP"}
 
 EXPORTS = ["cs_circ_apply", "cs_circ_apply_T", "cs_circ_norm_bound", "cs_ista_solve",
-           "cs_admm_solve", "cs_set_solver_path", "cs_check_device", "cs_timing_enable",
+           "cs_admm_solve", "cs_ista_solve_batched", "cs_set_solver_path", "cs_check_device", "cs_timing_enable",
            "cs_timing_read", "cs_last_error", "cs_version"]
 
 
@@ -46,6 +46,7 @@ def load():
         "cs_circ_norm_bound": [P, I64, P, P],
         "cs_ista_solve": [P, I64, I32, P, F, F, I32, P, P, P],
         "cs_admm_solve": [P, I64, I32, P, F, F, I32, I32, P, P, P, P, P],
+        "cs_ista_solve_batched": [I32, P, I32, P, P, P, P, P, P, I32, P, P],
         "cs_set_solver_path": [I32],
         "cs_check_device": [P],
         "cs_timing_enable": [I32],
@@ -141,6 +142,34 @@ def admm_solve(c, d, y, lam, rho, iters, x=None, z=None, u=None, warm=False, obj
                                 int(iters), int(bool(warm)), _ptr(x, "x", n), _ptr(z, "z", n),
                                 _ptr(u, "u", n), _ptr(obj, "obj", iters), _stream(c)))
     return x, z, u
+
+
+def batch_offsets(ns, d):
+    """Offsets of each signal in the concatenated n- and m-length arrays."""
+    import numpy as np
+    ns = np.asarray(ns, dtype=np.int64)
+    off_n = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)
+    off_m = np.concatenate([[0], np.cumsum(ns // d)[:-1]]).astype(np.int64)
+    return off_n, off_m
+
+
+def ista_solve_batched(ns, d, c_cat, y_cat, lam, tau, iters, x_cat=None):
+    """Batched ISTA over signals of lengths `ns` (concatenated inputs); lam and
+    tau are device arrays with one value per signal."""
+    import numpy as np
+    import torch
+    ns = np.ascontiguousarray(ns, dtype=np.int64)
+    off_n, off_m = batch_offsets(ns, d)
+    total_n, total_m = int(ns.sum()), int((ns // d).sum())
+    if x_cat is None:
+        x_cat = torch.empty(total_n, device=c_cat.device, dtype=torch.float32)
+    B = len(ns)
+    P = ctypes.c_void_p
+    _check(load().cs_ista_solve_batched(
+        B, P(ns.ctypes.data), d, P(off_n.ctypes.data), P(off_m.ctypes.data),
+        _ptr(c_cat, "c_cat", total_n), _ptr(y_cat, "y_cat", total_m), _ptr(lam, "lam", B), _ptr(tau, "tau", B),
+        int(iters), _ptr(x_cat, "x_cat", total_n), _stream(c_cat)))
+    return x_cat
 
 
 PATH_AUTO, PATH_TWO_PASS, PATH_PERSISTENT = 0, 1, 2

@@ -18,6 +18,7 @@ LIB = os.path.join(HERE, "libcscirc.so")
 ROW_LENGTHS = [16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192]   # pass A (N2)
 COL_LENGTHS = [8, 16, 32, 64, 128, 256, 512, 1024, 2048]            # pass B (N1)
 SOLVE_LOGN = list(range(7, 22))                                     # persistent solver, N = 2^L
+BATCH_D2 = [1, 2, 4]                                                # batched ISTA, d = 2 * D2
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -45,8 +46,10 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         units.append((os.path.join(CSRC, "inst_passB.hip"), os.path.join(BUILD, "passB_%d.o" % L), ["-DCS_LEN=%d" % L]))
     for L in SOLVE_LOGN:
         units.append((os.path.join(CSRC, "inst_solve.hip"), os.path.join(BUILD, "solve_%d.o" % L), ["-DCS_LOGN=%d" % L]))
+    for D2 in BATCH_D2:
+        units.append((os.path.join(CSRC, "inst_batch.hip"), os.path.join(BUILD, "batch_%d.o" % D2), ["-DCS_D2=%d" % D2]))
     units.append((os.path.join(CSRC, "runtime.hip"), os.path.join(BUILD, "runtime.o"), []))
-    units.sort(key=lambda u: ("solve" not in u[1], -len(u[1])))
+    units.sort(key=lambda u: ("solve" not in u[1] and "batch" not in u[1], -len(u[1])))
     jobs = jobs or min(16, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
         futs = [ex.submit(_run, [HIPCC] + FLAGS + extra + ["-c", src, "-o", obj]) for src, obj, extra in units]

@@ -114,29 +114,20 @@ __device__ __forceinline__ float2 tw_N(const PassBArgs& a, int e) {
 // Pass A.  Workgroup w owns rows {w, N1 - w}; workgroup 0 owns the two rows
 // that are their own mirror images, {0, N1/2}.  Rows are held in LDS slots 0
 // and 1.
-template <int N2, int OP, int D2>
-__global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
-  constexpr int T = kThreads;
+template <int N2, int OP, int D2, int T>
+__device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __restrict__ lds,
+                                        const float2* __restrict__ tws, unsigned tid) {
   constexpr int LD = N2 + kPadA;
   constexpr int EPT = (2 * N2 + T - 1) / T;           // row elements per thread
   constexpr bool GROUP = (OP == A_ISTA || OP == A_ADMM);
   constexpr int MC = N2 / D2;                         // alias classes per row (= m / N1)
   constexpr int GPT = GROUP ? (MC + 1 + T - 1) / T : 1;
-  // row-FFT stage twiddles W_{N2}^e: copied to LDS when both rows and the
-  // table fit in the 160 KiB of a CU, read from the global table otherwise
-  constexpr bool TW_LDS = (lds_padded(2 * LD) + N2) * 8 <= 160 * 1024 - 1024;
-  __shared__ float2 lds[lds_padded(2 * LD)];
-  __shared__ float2 tws_l[TW_LDS ? N2 : 1];
-  const float2* tws = TW_LDS ? tws_l : a.tw2;
-  const int tid = threadIdx.x;
-  const int w = blockIdx.x;
   const int N1 = a.N1;
   const int ra = w;                          // row in slot 0
   const int rb = w ? (N1 - w) : (N1 >> 1);   // row in slot 1
 
-  // Issue every global load of this workgroup before the first wait: the two
-  // rows, the row-FFT twiddles and (update modes) each class's c_hat, y_hat
-  // and split twiddles.
+  // Issue every global load before the first wait: the two rows and (update
+  // modes) each class's c_hat, y_hat and split twiddles.
   float2 rv[EPT];
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
@@ -144,15 +135,6 @@ __global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
     if ((2 * N2) % T == 0 || i < 2 * N2) {
       const int s = i / N2, p = i % N2;
       rv[k] = a.Y[(size_t)(s ? rb : ra) * N2 + p];
-    }
-  }
-  constexpr int TPT = TW_LDS ? (N2 + T - 1) / T : 1;
-  float2 tv[TPT];
-  if constexpr (TW_LDS) {
-#pragma unroll
-    for (int k = 0; k < TPT; ++k) {
-      const int i = tid + k * T;
-      if (N2 % T == 0 || i < N2) tv[k] = a.tw2[i];
     }
   }
   // class decode: mode 0 = row pair (w > 0); 1 = row 0; 2 = row N1/2 (w = 0)
@@ -186,13 +168,6 @@ __global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
   for (int k = 0; k < EPT; ++k) {
     const int i = tid + k * T;
     if ((2 * N2) % T == 0 || i < 2 * N2) lds[lp((i / N2) * LD + (i % N2))] = rv[k];
-  }
-  if constexpr (TW_LDS) {
-#pragma unroll
-    for (int k = 0; k < TPT; ++k) {
-      const int i = tid + k * T;
-      if (N2 % T == 0 || i < N2) tws_l[i] = tv[k];
-    }
   }
   __syncthreads();
   lds_fft<N2, 2, T, false, false, LD>(lds, tws, tid);
@@ -327,34 +302,40 @@ __global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
   }
 }
 
+// Row-pass kernel: workgroup w owns rows {w, N1 - w}; workgroup 0 owns the
+// two rows that are their own mirror images, {0, N1/2}.  The row-FFT stage
+// twiddles W_{N2}^e are copied to LDS when both rows and the table fit in the
+// 160 KiB of a CU, and read from the global table otherwise.
+template <int N2, int OP, int D2>
+__global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
+  constexpr int LD = N2 + kPadA;
+  constexpr bool TW_LDS = (lds_padded(2 * LD) + N2) * 8 <= 160 * 1024 - 1024;
+  __shared__ float2 lds[lds_padded(2 * LD)];
+  __shared__ float2 tws_l[TW_LDS ? N2 : 1];
+  if constexpr (TW_LDS) {
+    for (unsigned i = threadIdx.x; i < N2; i += kThreads) tws_l[i] = a.tw2[i];
+  }
+  __syncthreads();
+  rowpass<N2, OP, D2, kThreads>(a, blockIdx.x, lds, TW_LDS ? tws_l : a.tw2, threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Pass B.  Workgroup b owns columns j2 in [b*CB, b*CB + CB); LDS holds them
 // interleaved, element (column c, index i) at [i*CB + c].  Global accesses are
 // issued in register-staged chunks of CH elements per thread so that a chunk's
 // loads are all in flight before the first wait.
-template <int N1, int MODE>
-__global__ __launch_bounds__(kThreads) void k_passB(PassBArgs a) {
-  constexpr int T = kThreads;
+template <int N1, int MODE, int T>
+__device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __restrict__ lds,
+                                        const float2* __restrict__ tws, unsigned tid) {
   constexpr int CB = kColsPerBlock;
   constexpr int NE = N1 * CB;
   constexpr int EPT = (NE + T - 1) / T;
   constexpr int CH = EPT < 8 ? EPT : 8;
   constexpr bool FULL = (NE % T) == 0;
-  __shared__ float2 lds[lds_padded(NE)];
-  __shared__ float2 tws[N1];
-  const int tid = threadIdx.x;
-  const int j2_0 = blockIdx.x * CB;
+  const int j2_0 = blk * CB;
   const int N2 = a.N2;
   constexpr bool HAS_INV = (MODE == B_ISTA || MODE == B_ADMM || MODE == B_OUT_ALL || MODE == B_OUT_DEC);
 
-  {
-    constexpr int TPT = (N1 + T - 1) / T;
-#pragma unroll
-    for (int k = 0; k < TPT; ++k) {
-      const int i = tid + k * T;
-      if (N1 % T == 0 || i < N1) tws[i] = a.tw1[i];
-    }
-  }
   if constexpr (HAS_INV) {
 #pragma unroll
     for (int k0 = 0; k0 < EPT; k0 += CH) {
@@ -482,6 +463,16 @@ __global__ __launch_bounds__(kThreads) void k_passB(PassBArgs a) {
       }
     }
   }
+}
+
+// Column-pass kernel: workgroup b owns columns [8b, 8b + 8).
+template <int N1, int MODE>
+__global__ __launch_bounds__(kThreads) void k_passB(PassBArgs a) {
+  __shared__ float2 lds[lds_padded(N1 * kColsPerBlock)];
+  __shared__ float2 tws[N1];
+  for (unsigned i = threadIdx.x; i < N1; i += kThreads) tws[i] = a.tw1[i];
+  __syncthreads();
+  colpass<N1, MODE, kThreads>(a, blockIdx.x, lds, tws, threadIdx.x);
 }
 
 }  // namespace cs

@@ -20,4 +20,12 @@ hipError_t launch_solve(int alg, int d2, const SolveArgs& a, hipStream_t s);
 template <int LOGN>
 int solve_blocks_per_cu(int alg, int d2);
 
+struct BatchSig;
+// batched ISTA for decimation d = 2 * D2 (inst_batch.hip)
+template <int D2>
+hipError_t launch_batch_ista(const BatchSig* sigs, int count, unsigned* queue, int iters, int grid,
+                             hipStream_t s);
+template <int D2>
+int batch_blocks_per_cu();
+
 }  // namespace cs

@@ -22,6 +22,10 @@
 #include "cscirc.h"
 #include "launch.hpp"
 #include "solve_persistent.hpp"
+#include "batch.hpp"
+
+#include <algorithm>
+#include <numeric>
 
 namespace cs {
 namespace {
@@ -231,9 +235,9 @@ hipEvent_t take_event() {
   return e;
 }
 
-enum TimedKind { T_A_ISTA = 0, T_B_ISTA, T_A_ADMM, T_B_ADMM, T_S_ISTA, T_S_ADMM, T_COUNT };
+enum TimedKind { T_A_ISTA = 0, T_B_ISTA, T_A_ADMM, T_B_ADMM, T_S_ISTA, T_S_ADMM, T_BATCH, T_COUNT };
 const char* kTimedNames[T_COUNT] = {"passA_ista", "passB_ista", "passA_admm", "passB_admm",
-                                    "solve_ista", "solve_admm"};
+                                    "solve_ista", "solve_admm", "batch_ista"};
 
 template <class F>
 hipError_t timed(int kind, hipStream_t s, F&& launch) {
@@ -331,6 +335,38 @@ SolveArgs solve_args(const Plan& P) {
   return a;
 }
 
+// Batched solves: per device, a grow-only scratch buffer (spectrum and
+// tables of every signal), the descriptor array of the last batch and the
+// work-queue counter.
+struct BatchState {
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  BatchSig* sigs = nullptr;
+  size_t sigs_cap = 0;
+  std::vector<BatchSig> last;   // descriptors currently on the device
+  unsigned* queue = nullptr;
+};
+std::map<int, BatchState> g_batch;
+
+hipError_t launch_batch_dispatch(int d2, const BatchSig* sigs, int count, unsigned* queue, int iters,
+                                 int grid, hipStream_t s) {
+  switch (d2) {
+    case 1: return launch_batch_ista<1>(sigs, count, queue, iters, grid, s);
+    case 2: return launch_batch_ista<2>(sigs, count, queue, iters, grid, s);
+    case 4: return launch_batch_ista<4>(sigs, count, queue, iters, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int batch_blocks_dispatch(int d2) {
+  switch (d2) {
+    case 1: return batch_blocks_per_cu<1>();
+    case 2: return batch_blocks_per_cu<2>();
+    case 4: return batch_blocks_per_cu<4>();
+    default: return 0;
+  }
+}
+
 __global__ void k_max_abs2(const float2* __restrict__ t, int count, float* __restrict__ out) {
   __shared__ float red[256];
   float m = 0.0f;
@@ -368,6 +404,113 @@ extern "C" {
 const char* cs_last_error(void) { return g_err.c_str(); }
 
 int32_t cs_version(void) { return 100; }
+
+cs_status cs_ista_solve_batched(int32_t count, const int64_t* n_host, int32_t d, const int64_t* off_n_host,
+                                const int64_t* off_m_host, const float* c_cat, const float* y_cat,
+                                const float* lambda_dev, const float* tau_dev, int32_t iters, float* x_cat,
+                                cs_stream stream) {
+  if (count < 0) return fail(CS_EINVAL, "count=%d must be >= 0", count);
+  if (count == 0) { g_err.clear(); return CS_OK; }
+  if (!n_host || !off_n_host || !off_m_host) return fail(CS_EINVAL, "size or offset array is NULL");
+  if (!c_cat || !y_cat || !lambda_dev || !tau_dev || !x_cat) return fail(CS_EINVAL, "a device array is NULL");
+  if (d != 2 && d != 4 && d != 8) return fail(CS_EINVAL, "d=%d must be 2, 4 or 8 for batched solves", d);
+  if (iters < 0) return fail(CS_EINVAL, "iters=%d must be >= 0", iters);
+  for (int i = 0; i < count; ++i) {
+    const int64_t n = n_host[i];
+    if (!is_pow2(n) || n < (int64_t(1) << (kBMinLogN + 1)) || n > (int64_t(1) << (kBMaxLogN + 1)))
+      return fail(CS_EINVAL, "n[%d]=%lld must be a power of two in [2^%d, 2^%d]", i, (long long)n,
+                  kBMinLogN + 1, kBMaxLogN + 1);
+    if (off_n_host[i] < 0 || (off_n_host[i] & 1) || off_m_host[i] < 0)
+      return fail(CS_EINVAL, "offsets of signal %d must be >= 0 (off_n even)", i);
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int dev = 0;
+  CS_HIP(hipGetDevice(&dev));
+  // tables per distinct length (the per-(n, d) plans)
+  std::map<int64_t, Plan*> plans;
+  for (int i = 0; i < count; ++i) {
+    if (plans.count(n_host[i])) continue;
+    Plan* P = nullptr;
+    cs_status st = get_plan(n_host[i], d, &P);
+    if (st != CS_OK) return st;
+    plans[n_host[i]] = P;
+  }
+  // longest signals first: the queue hands them out first and the launch's
+  // tail is made of short signals
+  std::vector<int> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n_host[a] > n_host[b]; });
+  size_t need = 0;
+  std::vector<size_t> off(count);
+  for (int i = 0; i < count; ++i) {
+    const int64_t N = n_host[i] / 2;
+    off[i] = need;
+    need += size_t((3 * N + 2 + 63) & ~int64_t(63)) * sizeof(float2);
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  BatchState& B = g_batch[dev];
+  if (B.scratch_bytes < need) {
+    CS_HIP(hipStreamSynchronize(s));
+    if (B.scratch) CS_HIP(hipFree(B.scratch));
+    B.scratch = nullptr;
+    B.scratch_bytes = 0;
+    hipError_t e = hipMalloc(&B.scratch, need);
+    if (e != hipSuccess) return fail(CS_ENOMEM, "hipMalloc of %zu bytes of batch scratch failed", need);
+    B.scratch_bytes = need;
+    B.last.clear();
+  }
+  if (!B.queue) {
+    hipError_t e = hipMalloc(&B.queue, 256);
+    if (e != hipSuccess) return fail(CS_ENOMEM, "hipMalloc of the batch queue failed");
+  }
+  std::vector<BatchSig> sig(count);
+  for (int k = 0; k < count; ++k) {
+    const int i = order[k];
+    const Plan& P = *plans[n_host[i]];
+    BatchSig& g = sig[k];
+    std::memset(&g, 0, sizeof g);
+    float2* base = reinterpret_cast<float2*>(static_cast<char*>(B.scratch) + off[i]);
+    g.c = c_cat + off_n_host[i];
+    g.y = y_cat + off_m_host[i];
+    g.x = x_cat + off_n_host[i];
+    g.lam = lambda_dev + i;
+    g.tau = tau_dev + i;
+    g.Y = base;
+    g.chat = base + P.N;
+    g.yhat = base + 2 * P.N + 1;
+    g.tw1 = P.tw1; g.tw2 = P.tw2; g.twlo = P.twlo; g.twhi = P.twhi; g.twk1 = P.twk1; g.twp = P.twp;
+    g.logN = P.logN;
+    g.lo_bits = P.lo_bits;
+  }
+  // descriptors: upload only when they differ from what the device holds
+  const bool same = B.last.size() == sig.size() &&
+                    std::memcmp(B.last.data(), sig.data(), sig.size() * sizeof(BatchSig)) == 0;
+  if (!same) {
+    CS_HIP(hipStreamSynchronize(s));
+    if (B.sigs_cap < sig.size()) {
+      if (B.sigs) CS_HIP(hipFree(B.sigs));
+      B.sigs = nullptr;
+      B.sigs_cap = 0;
+      hipError_t e = hipMalloc(&B.sigs, sig.size() * sizeof(BatchSig));
+      if (e != hipSuccess) return fail(CS_ENOMEM, "hipMalloc of batch descriptors failed");
+      B.sigs_cap = sig.size();
+    }
+    CS_HIP(hipMemcpy(B.sigs, sig.data(), sig.size() * sizeof(BatchSig), hipMemcpyHostToDevice));
+    B.last = sig;
+  }
+  int cus = 0;
+  CS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int per = batch_blocks_dispatch(d / 2);
+  if (per < 1) return fail(CS_EHIP, "batched kernel cannot be resident on this device");
+  const int grid = std::min(count, cus * per);
+  cs_status st = fill(reinterpret_cast<float*>(B.queue), 1, 0.0f, s);
+  if (st != CS_OK) return st;
+  BatchSig* dsig = B.sigs;
+  unsigned* q = B.queue;
+  CS_LAUNCH(timed(T_BATCH, s, [&] { return launch_batch_dispatch(d / 2, dsig, count, q, iters, grid, s); }));
+  g_err.clear();
+  return CS_OK;
+}
 
 cs_status cs_set_solver_path(int32_t path) {
   if (path < 0 || path > 2) return fail(CS_EINVAL, "path=%d must be 0, 1 or 2", path);
