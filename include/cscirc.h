@@ -67,7 +67,13 @@ cs_status cs_circ_norm_bound(const float* c, int64_t n, float* out, cs_stream st
  * eta is the soft threshold of Eq. 4 (strict comparison).  The threshold is
  * tau*lambda (proximal-gradient reading of the LASSO of Eq. 3 with alpha =
  * lambda).  y: m.  x: n, output x(iters) (zero when iters == 0).
- * Requires lambda >= 0, tau > 0, iters >= 0.  obj must be NULL.  */
+ * obj: NULL, or a device array of `iters` floats that receives the LASSO
+ * objective of Eq. 3 (halved) along the iterates,
+ *     obj[t-1] = F(x(t)) = 1/2 ||y - A x(t)||^2 + lambda ||x(t)||_1,
+ * the residual taken by Parseval from the m-point spectrum the iteration
+ * already forms and summed in double per workgroup.  A trace runs the
+ * two-pass schedule (one row and one column launch per iteration).
+ * Requires lambda >= 0, tau > 0, iters >= 0.  */
 cs_status cs_ista_solve(const float* c, int64_t n, int32_t d, const float* y, float lambda,
                         float tau, int32_t iters, float* x, float* obj, cs_stream stream);
 
@@ -81,7 +87,11 @@ cs_status cs_ista_solve(const float* c, int64_t n, int32_t d, const float* y, fl
  * passed in.  x, z, u: n each, outputs x(iters), z(iters), u(iters); u is
  * also used as the dual state during the solve.  With iters == 0 and warm ==
  * 0 all three are zeroed; with warm != 0 they are left as passed.
- * Requires lambda >= 0, rho > 0, iters >= 0.  obj must be NULL.  */
+ * obj: NULL, or a device array of `iters` floats that receives
+ *     obj[t-1] = F(x(t)) = 1/2 ||y - A x(t)||^2 + lambda ||x(t)||_1
+ * for the x-update iterate (Eq. 3 halved; the same Parseval residual as
+ * ISTA's).  A trace runs the two-pass schedule.
+ * Requires lambda >= 0, rho > 0, iters >= 0.  */
 cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, float lambda,
                         float rho, int32_t iters, int32_t warm, float* x, float* z, float* u,
                         float* obj, cs_stream stream);
@@ -103,6 +113,27 @@ cs_status cs_ista_solve_batched(int32_t count, const int64_t* n_host, int32_t d,
                                 const int64_t* off_m_host, const float* c_cat, const float* y_cat,
                                 const float* lambda_dev, const float* tau_dev, int32_t iters, float* x_cat,
                                 cs_stream stream);
+
+/* Differentiable unrolled ISTA (Alg. 1 with learnable per-iteration
+ * parameters) over a batch of Bt signals that share one operator A = P C:
+ *     x_0 = 0,  v_t = x_{t-1} + tau[t] A^T (y_b - A x_{t-1}),
+ *     x_t = eta_{tau[t] lam[t]}(v_t),   t = 1..K  (0-based arrays).
+ * lam and tau are DEVICE arrays of K floats; y is Bt x m row-major; xK is
+ * Bt x n.  The forward pass stores x at t = every, 2 every, ... (< K) in the
+ * caller's checkpoint area of cs_unrolled_ckpt_bytes() bytes.  The backward
+ * pass takes g_xK = dL/dx_K (Bt x n), recomputes each segment of `every`
+ * steps from its checkpoint and runs the adjoint of the recursion, writing
+ * g_lam (K), g_tau (K) and g_y (Bt x m), all device arrays.  The threshold's
+ * derivative is taken as 0 where |v_t| equals the threshold.  A workspace per
+ * (device, n, d, Bt, every) is allocated on first use (about
+ * (3 + 2 every) Bt n floats plus 3 Bt n/2 complex) and kept.  */
+size_t cs_unrolled_ckpt_bytes(int64_t n, int32_t d, int32_t Bt, int32_t K, int32_t every);
+cs_status cs_unrolled_ista_fwd(const float* c, int64_t n, int32_t d, int32_t Bt, const float* y, const float* lam,
+                               const float* tau, int32_t K, int32_t every, float* xK, void* ckpt,
+                               cs_stream stream);
+cs_status cs_unrolled_ista_bwd(const float* c, int64_t n, int32_t d, int32_t Bt, const float* y, const float* lam,
+                               const float* tau, int32_t K, int32_t every, const void* ckpt, const float* g_xK,
+                               float* g_lam, float* g_tau, float* g_y, cs_stream stream);
 
 /* Solver schedule.  For 2^8 <= n <= 2^22 a solve runs as ONE cooperative
  * launch: all iterations in a persistent kernel whose workgroups keep the

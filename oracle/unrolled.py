@@ -58,8 +58,13 @@ def loss(XK, Xstar):
     return float(np.sum((XK - Xstar) ** 2))
 
 
-def backward(op, Y, lam, tau, K, Xstar):
-    """Gradients of L with respect to lam (K), tau (K) and Y (B x m)."""
+def backward(op, Y, lam, tau, K, Xstar, flip=()):
+    """Gradients of L with respect to lam (K), tau (K) and Y (B x m).
+
+    `flip` names entries (t, b, i) whose mask M_t is inverted.  At an entry
+    with |v_t| within rounding of theta_t the threshold decision of a lower
+    precision implementation may go either way; both choices give a valid
+    (one-sided) derivative, and a comparison accepts any of them."""
     XK, rec = forward(op, Y, lam, tau, K)
     xbar = 2.0 * (XK - np.asarray(Xstar, np.float64))
     g_lam = np.zeros(K)
@@ -69,6 +74,9 @@ def backward(op, Y, lam, tau, K, Xstar):
         Xp, G, V = rec[t]
         th = tau[t] * lam[t]
         Mk = (np.abs(V) > th).astype(np.float64)
+        for (tf, b, i) in flip:
+            if tf == t:
+                Mk[b, i] = 1.0 - Mk[b, i]
         vbar = Mk * xbar
         thbar = -float(np.sum(np.sign(V) * Mk * xbar))
         g_lam[t] = tau[t] * thbar
@@ -83,3 +91,13 @@ def min_margin(op, Y, lam, tau, K):
     """Smallest | |v_t| - theta_t | over all steps (distance to a kink)."""
     _, rec = forward(op, Y, lam, tau, K)
     return min(float(np.min(np.abs(np.abs(V) - tau[t] * lam[t]))) for t, (_, _, V) in enumerate(rec))
+
+
+def ambiguous(op, Y, lam, tau, K, delta):
+    """Entries (t, b, i) with | |v_t| - theta_t | < delta."""
+    _, rec = forward(op, Y, lam, tau, K)
+    out = []
+    for t, (_, _, V) in enumerate(rec):
+        bb, ii = np.nonzero(np.abs(np.abs(V) - tau[t] * lam[t]) < delta)
+        out += [(t, int(b), int(i)) for b, i in zip(bb, ii)]
+    return out

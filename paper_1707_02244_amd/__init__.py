@@ -4,5 +4,15 @@ The compute path is the HIP library libcscirc.so (C ABI in include/cscirc.h);
 this package only marshals torch tensors into it.
 """
 from ._lib import (CsError, LIB_PATH, EXPORTS, load, circ_apply, circ_apply_T,  # noqa: F401
-                   circ_norm_bound, ista_solve, admm_solve, ista_solve_batched, batch_offsets, timing_enable, timing_read, version,
+                   circ_norm_bound, ista_solve, admm_solve, ista_solve_batched, batch_offsets,
+                   unrolled_ckpt_bytes, unrolled_ista_fwd, unrolled_ista_bwd, timing_enable, timing_read, version,
                    set_solver_path, check_device, PATH_AUTO, PATH_TWO_PASS, PATH_PERSISTENT)
+
+
+def __getattr__(name):
+    if name == "UnrolledISTA":
+        from . import _lib
+        cls = _lib._unrolled_function()
+        globals()["UnrolledISTA"] = cls
+        return cls
+    raise AttributeError(name)

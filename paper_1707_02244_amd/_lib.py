@@ -17,7 +17,8 @@ CS_OK, CS_EINVAL, CS_ENOMEM, CS_EHIP, CS_ENOTSUP = 0, -1, -2, -3, -4
 _NAMES = {CS_EINVAL: "CS_EINVAL", CS_ENOMEM: "CS_ENOMEM", CS_EHIP: "CS_EHIP", CS_ENOTSUP: "CS_ENOTSUP"}
 
 EXPORTS = ["cs_circ_apply", "cs_circ_apply_T", "cs_circ_norm_bound", "cs_ista_solve",
-           "cs_admm_solve", "cs_ista_solve_batched", "cs_set_solver_path", "cs_check_device", "cs_timing_enable",
+           "cs_admm_solve", "cs_ista_solve_batched", "cs_unrolled_ckpt_bytes", "cs_unrolled_ista_fwd",
+           "cs_unrolled_ista_bwd", "cs_set_solver_path", "cs_check_device", "cs_timing_enable",
            "cs_timing_read", "cs_last_error", "cs_version"]
 
 
@@ -47,6 +48,9 @@ def load():
         "cs_ista_solve": [P, I64, I32, P, F, F, I32, P, P, P],
         "cs_admm_solve": [P, I64, I32, P, F, F, I32, I32, P, P, P, P, P],
         "cs_ista_solve_batched": [I32, P, I32, P, P, P, P, P, P, I32, P, P],
+        "cs_unrolled_ckpt_bytes": [I64, I32, I32, I32, I32],
+        "cs_unrolled_ista_fwd": [P, I64, I32, I32, P, P, P, I32, I32, P, P, P],
+        "cs_unrolled_ista_bwd": [P, I64, I32, I32, P, P, P, I32, I32, P, P, P, P, P, P],
         "cs_set_solver_path": [I32],
         "cs_check_device": [P],
         "cs_timing_enable": [I32],
@@ -59,6 +63,7 @@ def load():
         fn.argtypes = args
         fn.restype = ctypes.c_int
     lib.cs_last_error.restype = ctypes.c_char_p
+    lib.cs_unrolled_ckpt_bytes.restype = ctypes.c_size_t
     _lib = lib
     return lib
 
@@ -172,6 +177,67 @@ def ista_solve_batched(ns, d, c_cat, y_cat, lam, tau, iters, x_cat=None):
     return x_cat
 
 
+def unrolled_ckpt_bytes(n, d, batch, K, every):
+    return int(load().cs_unrolled_ckpt_bytes(n, d, batch, K, every))
+
+
+def unrolled_ista_fwd(c, d, y, lam, tau, K, every, xK=None, ckpt=None):
+    """Forward of K unrolled ISTA steps for a batch y (Bt x m) sharing c.
+    Returns (x_K, checkpoints)."""
+    import torch
+    n = c.numel()
+    Bt = y.shape[0]
+    if xK is None:
+        xK = torch.empty(Bt, n, device=c.device, dtype=torch.float32)
+    nb = unrolled_ckpt_bytes(n, d, Bt, K, every)
+    if ckpt is None:
+        ckpt = torch.empty(max(nb // 4, 1), device=c.device, dtype=torch.float32)
+    _check(load().cs_unrolled_ista_fwd(_ptr(c, "c"), n, d, Bt, _ptr(y, "y", Bt * (n // d)), _ptr(lam, "lam", K),
+                                       _ptr(tau, "tau", K), int(K), int(every), _ptr(xK, "xK", Bt * n),
+                                       _ptr(ckpt, "ckpt"), _stream(c)))
+    return xK, ckpt
+
+
+def unrolled_ista_bwd(c, d, y, lam, tau, K, every, ckpt, g_xK):
+    """Reverse pass: (dL/dlam, dL/dtau, dL/dy) from dL/dx_K."""
+    import torch
+    n = c.numel()
+    Bt = y.shape[0]
+    g_lam = torch.empty(K, device=c.device, dtype=torch.float32)
+    g_tau = torch.empty(K, device=c.device, dtype=torch.float32)
+    g_y = torch.empty_like(y)
+    _check(load().cs_unrolled_ista_bwd(_ptr(c, "c"), n, d, Bt, _ptr(y, "y", Bt * (n // d)), _ptr(lam, "lam", K),
+                                       _ptr(tau, "tau", K), int(K), int(every), _ptr(ckpt, "ckpt"),
+                                       _ptr(g_xK, "g_xK", Bt * n), _ptr(g_lam, "g_lam", K), _ptr(g_tau, "g_tau", K),
+                                       _ptr(g_y, "g_y"), _stream(c)))
+    return g_lam, g_tau, g_y
+
+
+def _unrolled_function():
+    import torch
+
+    class UnrolledISTA(torch.autograd.Function):
+        """x_K of K unrolled ISTA steps; differentiable in y, lam and tau.
+        Usage: UnrolledISTA.apply(y, lam, tau, c, d, K, every)."""
+
+        @staticmethod
+        def forward(ctx, y, lam, tau, c, d, K, every):
+            y, lam, tau = y.contiguous(), lam.contiguous(), tau.contiguous()
+            xK, ckpt = unrolled_ista_fwd(c, d, y, lam, tau, K, every)
+            ctx.save_for_backward(y, lam, tau, c, ckpt)
+            ctx.cfg = (d, K, every)
+            return xK
+
+        @staticmethod
+        def backward(ctx, g):
+            y, lam, tau, c, ckpt = ctx.saved_tensors
+            d, K, every = ctx.cfg
+            g_lam, g_tau, g_y = unrolled_ista_bwd(c, d, y, lam, tau, K, every, ckpt, g.contiguous())
+            return g_y, g_lam, g_tau, None, None, None, None
+
+    return UnrolledISTA
+
+
 PATH_AUTO, PATH_TWO_PASS, PATH_PERSISTENT = 0, 1, 2
 
 
@@ -199,6 +265,12 @@ def timing_read(kernel):
     ms = ctypes.c_double(0.0)
     _check(load().cs_timing_read(kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
     return int(n.value), float(ms.value)
+
+
+def __getattr__(name):
+    if name == "UnrolledISTA":
+        return _unrolled_function()
+    raise AttributeError(name)
 
 
 def version():

@@ -1,5 +1,6 @@
 // Pass-B instantiation for one column length N1 = CS_LEN.
 #include "launch.hpp"
+#include "unrolled.hpp"
 
 #ifndef CS_LEN
 #error "compile with -DCS_LEN=<column length>"
@@ -19,6 +20,24 @@ hipError_t launch_passB<CS_LEN>(int mode, int grid, const PassBArgs& a, hipStrea
     case B_ADMM: k_passB<L, B_ADMM><<<g, b, 0, s>>>(a); break;
     case B_OUT_ALL: k_passB<L, B_OUT_ALL><<<g, b, 0, s>>>(a); break;
     case B_OUT_DEC: k_passB<L, B_OUT_DEC><<<g, b, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_ucol<CS_LEN>(int mode, int grid, int batch, const PassBArgs& a, const UStride& st,
+                               hipStream_t s) {
+  constexpr int L = CS_LEN;
+  const dim3 g(grid, batch), b(kThreads);
+  switch (mode) {
+    case B_FWD_REAL: k_ucol<L, B_FWD_REAL><<<g, b, 0, s>>>(a, st); break;
+    case B_FWD_UP: k_ucol<L, B_FWD_UP><<<g, b, 0, s>>>(a, st); break;
+    case B_ISTA: k_ucol<L, B_ISTA><<<g, b, 0, s>>>(a, st); break;
+    case B_ISTA_REC: k_ucol<L, B_ISTA_REC><<<g, b, 0, s>>>(a, st); break;
+    case B_ADJ_V: k_ucol<L, B_ADJ_V><<<g, b, 0, s>>>(a, st); break;
+    case B_ADJ_X: k_ucol<L, B_ADJ_X><<<g, b, 0, s>>>(a, st); break;
+    case B_OUT_DEC: k_ucol<L, B_OUT_DEC><<<g, b, 0, s>>>(a, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -56,6 +56,12 @@ enum OpA : int {
   A_MUL = 2,    // multiply by c_hat      (C x)
   A_MULC = 3,   // multiply by conj(c_hat) (C^T x)
   A_SPEC = 4,   // write the half spectrum X_k, k in [0, N], to a table
+  A_ADJ = 5,    // adjoint step: S = A v (m-point spectrum), ybar += tau S,
+                //   output -tau A^T A v   (the ISTA update with y = 0)
+  A_TILE = 6,   // output the n-point spectrum of P^T r from r's m-point
+                //   spectrum (the table in `ybar`)
+  A_RES = 7,    // objective trace only: sum |Y_hat - S|^2 of the current
+                //   iterate, no update
 };
 
 enum ModeB : int {
@@ -66,6 +72,9 @@ enum ModeB : int {
   B_ADMM = 4,      // Y -> inverse -> z, u update -> forward(z - u) -> Y (or write x, z)
   B_OUT_ALL = 5,   // Y -> inverse -> write all n reals
   B_OUT_DEC = 6,   // Y -> inverse -> write every d-th real (m values)
+  B_ISTA_REC = 7,  // B_ISTA that also records v_t = x + step and the step
+  B_ADJ_V = 8,     // xbar -> vbar = M_t * xbar, partial sums -> forward -> Y
+  B_ADJ_X = 9,     // Y -> inverse -> xbar = vbar + (-tau A^T A vbar)
 };
 
 struct PassAArgs {
@@ -83,6 +92,13 @@ struct PassAArgs {
   float inv_d;             // 1/d
   float tau;               // ISTA step
   float rho, inv_rho, d_rho;
+  const float* tau_dev;    // per-iteration steps (unrolled ISTA); used when set
+  int t;                   // iteration index into tau_dev
+  float2* ybar;            // A_ADJ: accumulated m-point spectrum; A_TILE: source
+  double* res;             // objective trace (A_ISTA, A_ADMM, A_RES; when set):
+                           //   res[w] = sum over workgroup w's m-point bins of
+                           //   |Y_hat - S|^2, S = DFT_m(A x) of the iterate
+                           //   (ISTA: the input x; ADMM: the updated x)
 };
 
 struct PassBArgs {
@@ -101,7 +117,32 @@ struct PassBArgs {
   float* u;                // state (n), read and written: B_ISTA x, B_ADMM u
   float thr;               // threshold (ISTA: tau*lam; ADMM: lam/rho)
   int last;                // final iteration: write outputs, skip the forward
+  const float* tau_dev;    // per-iteration parameters (unrolled ISTA): the
+  const float* lam_dev;    //   threshold is tau_dev[t] * lam_dev[t] when set
+  int t;
+  float* rv;               // B_ISTA_REC: v_t out; B_ADJ_V: v_t in
+  float* rd;               // B_ISTA_REC: step out; B_ADJ_V: step in
+  float* xbar;             // B_ADJ_V: in; B_ADJ_X: out
+  float* vbar;             // B_ADJ_V: out; B_ADJ_X: in
+  double* part;            // B_ADJ_V: per-workgroup partial sums (2 values)
+  int part_q;              //   stride between the two sums
+  double* l1;              // objective trace (B_ISTA, B_ADMM; when set):
+                           //   l1[b] = sum of |x| over workgroup b's samples
 };
+
+// Sum of v over the workgroup, returned to thread 0 (all threads call it).
+template <int T>
+__device__ __forceinline__ double block_sum(double v, unsigned tid) {
+  __shared__ double red[T / 64];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (tid == 0)
+    for (int w = 0; w < T / 64; ++w) r += red[w];
+  __syncthreads();
+  return r;
+}
 
 // ---------------------------------------------------------------------------
 // Four-step twiddle W_N^e from a two-level table.
@@ -119,10 +160,13 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
                                         const float2* __restrict__ tws, unsigned tid) {
   constexpr int LD = N2 + kPadA;
   constexpr int EPT = (2 * N2 + T - 1) / T;           // row elements per thread
-  constexpr bool GROUP = (OP == A_ISTA || OP == A_ADMM);
+  constexpr bool GROUP = (OP == A_ISTA || OP == A_ADMM || OP == A_ADJ || OP == A_TILE || OP == A_RES);
+  constexpr bool NEED_C = (OP == A_ISTA || OP == A_ADMM || OP == A_ADJ || OP == A_RES);
+  constexpr bool HAS_RES = (OP == A_ISTA || OP == A_ADMM || OP == A_RES);
   constexpr int MC = N2 / D2;                         // alias classes per row (= m / N1)
   constexpr int GPT = GROUP ? (MC + 1 + T - 1) / T : 1;
   const int N1 = a.N1;
+  const float tau = a.tau_dev ? a.tau_dev[a.t] : a.tau;
   const int ra = w;                          // row in slot 0
   const int rb = w ? (N1 - w) : (N1 >> 1);   // row in slot 1
 
@@ -157,10 +201,13 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
           const int p = k2 + l * M;
           const int q = (mode == 1) ? ((N2 - p) & (N2 - 1)) : (N2 - 1 - p);
           gw[k][l] = cmul(wk1, a.twp[p]);
-          gca[k][l] = a.chat[(size_t)rowa * N2 + p];
-          gcb[k][l] = (mode == 1 && p == 0) ? a.chat[a.N] : a.chat[(size_t)rowb * N2 + q];
+          if constexpr (NEED_C) {
+            gca[k][l] = a.chat[(size_t)rowa * N2 + p];
+            gcb[k][l] = (mode == 1 && p == 0) ? a.chat[a.N] : a.chat[(size_t)rowb * N2 + q];
+          }
         }
-        gy[k] = a.yhat[(size_t)rowa * N2 + k2];
+        if constexpr (OP == A_ISTA || OP == A_ADMM || OP == A_RES) gy[k] = a.yhat[(size_t)rowa * N2 + k2];
+        else if constexpr (OP == A_TILE) gy[k] = a.ybar[(size_t)rowa * N2 + k2];
       }
     }
   }
@@ -172,6 +219,9 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
   __syncthreads();
   lds_fft<N2, 2, T, false, false, LD>(lds, tws, tid);
 
+  // objective trace: this thread's sum of weight * |Y_hat - S|^2; a class
+  // stands for m-point bins k' and m - k' (weight 2) unless k' is 0 or m/2
+  float res_acc = 0.0f;
   if constexpr (GROUP) {
     // Alias classes.  For w > 0: class k' = w + N1*k2, k2 < M, has a-bins at
     // row w positions k2 + l*M and b-bins at row N1-w positions N2-1-k2-l*M.
@@ -187,6 +237,7 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
       else if (g <= (M >> 1)) { sa = 0; sb = 0; k2 = g; mode = 1; }
       else { sa = 1; sb = 1; k2 = g - (M >> 1) - 1; mode = 2; }
       const bool write_b = !(mode == 1 && (k2 == 0 || k2 == (M >> 1)));
+      const float res_w = write_b ? 2.0f : 1.0f;
       float2 Xa[D2], Xb[D2];
       int pa[D2], qb[D2];
 #pragma unroll
@@ -202,21 +253,46 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
         Xa[l] = cadd(P, wq);
         Xb[l] = cconj(csub(P, wq));
       }
-      const float2 yk = gy[k];
       float2 Va[D2], Vb[D2];
-      if constexpr (OP == A_ISTA) {
+      if constexpr (OP == A_RES) {
         float2 sa_ = c2(0.f, 0.f), sb_ = c2(0.f, 0.f);
 #pragma unroll
         for (int l = 0; l < D2; ++l) { sa_ = cadd(sa_, cmul(gca[k][l], Xa[l])); sb_ = cadd(sb_, cmul(gcb[k][l], Xb[l])); }
         const float2 S = cscale(cadd(sa_, cconj(sb_)), a.inv_d);
-        const float2 E = cscale(csub(yk, S), a.tau);
+        res_acc += res_w * cabs2(csub(gy[k], S));
+        continue;
+      } else if constexpr (OP == A_ISTA || OP == A_ADJ) {
+        // S = A x in the m-point domain; ISTA: tau A^T (y - A x);
+        // adjoint: -tau A^T A x, and tau A x accumulated into ybar
+        float2 sa_ = c2(0.f, 0.f), sb_ = c2(0.f, 0.f);
+#pragma unroll
+        for (int l = 0; l < D2; ++l) { sa_ = cadd(sa_, cmul(gca[k][l], Xa[l])); sb_ = cadd(sb_, cmul(gcb[k][l], Xb[l])); }
+        const float2 S = cscale(cadd(sa_, cconj(sb_)), a.inv_d);
+        float2 E;
+        if constexpr (OP == A_ISTA) {
+          const float2 r = csub(gy[k], S);
+          res_acc += res_w * cabs2(r);
+          E = cscale(r, tau);
+        } else {
+          E = cscale(S, -tau);
+          const int rowa = w ? w : (mode == 1 ? 0 : (N1 >> 1));
+          float2* yb = a.ybar + (size_t)rowa * N2 + k2;
+          *yb = cadd(*yb, cscale(S, tau));
+        }
         const float2 Ec = cconj(E);
 #pragma unroll
         for (int l = 0; l < D2; ++l) {
           Va[l] = cconjmul(gca[k][l], E);
           Vb[l] = cconjmul(gcb[k][l], Ec);
         }
+      } else if constexpr (OP == A_TILE) {
+        // the n-point spectrum of P^T r is r's m-point spectrum repeated over
+        // the d bins of each alias class (conjugated on the mirrored bins)
+        const float2 r = gy[k], rc = cconj(gy[k]);
+#pragma unroll
+        for (int l = 0; l < D2; ++l) { Va[l] = r; Vb[l] = rc; }
       } else {
+        const float2 yk = gy[k];
         float2 Qa[D2], Qb[D2];
         const float2 ykc = cconj(yk);
         float2 ra_ = c2(0.f, 0.f), rb_ = c2(0.f, 0.f);
@@ -235,6 +311,13 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
         for (int l = 0; l < D2; ++l) {
           Va[l] = cscale(csub(Qa[l], cconjmul(gca[k][l], Tq)), a.inv_rho);
           Vb[l] = cscale(csub(Qb[l], cconjmul(gcb[k][l], Tc)), a.inv_rho);
+        }
+        if (a.res) {
+          // residual of the updated x: S' = (sum c_a X'_a + conj sum c_b X'_b) / d
+          float2 s1 = c2(0.f, 0.f), s2 = c2(0.f, 0.f);
+#pragma unroll
+          for (int l = 0; l < D2; ++l) { s1 = cadd(s1, cmul(gca[k][l], Va[l])); s2 = cadd(s2, cmul(gcb[k][l], Vb[l])); }
+          res_acc += res_w * cabs2(csub(yk, cscale(cadd(s1, cconj(s2)), a.inv_d)));
         }
       }
       // inverse split, scaled by 1/n (1/2 of the split times 1/N of the inverse)
@@ -288,7 +371,13 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
       }
     }
   }
-  if constexpr (OP != A_SPEC) {
+  if constexpr (HAS_RES) {
+    if (a.res) {
+      const double r = block_sum<T>(double(res_acc), tid);
+      if (tid == 0) a.res[w] = r;
+    }
+  }
+  if constexpr (OP != A_SPEC && OP != A_RES) {
     __syncthreads();
     lds_fft<N2, 2, T, true, false, LD>(lds, tws, tid);
 #pragma unroll
@@ -334,7 +423,8 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
   constexpr bool FULL = (NE % T) == 0;
   const int j2_0 = blk * CB;
   const int N2 = a.N2;
-  constexpr bool HAS_INV = (MODE == B_ISTA || MODE == B_ADMM || MODE == B_OUT_ALL || MODE == B_OUT_DEC);
+  constexpr bool HAS_INV = (MODE == B_ISTA || MODE == B_ADMM || MODE == B_OUT_ALL || MODE == B_OUT_DEC ||
+                            MODE == B_ISTA_REC || MODE == B_ADJ_X);
 
   if constexpr (HAS_INV) {
 #pragma unroll
@@ -360,11 +450,12 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
     lds_fft<N1, CB, T, true, true, N1>(lds, tws, tid);
     // time domain: lds[lp(j1*CB + c)] = (x_{2j}, x_{2j+1}), j = N2*j1 + j2_0 + c
     bool fwd = true;
-    if constexpr (MODE == B_ISTA || MODE == B_ADMM) {
+    if constexpr (MODE == B_ISTA || MODE == B_ADMM || MODE == B_ISTA_REC) {
       // ISTA: lds holds tau A^T r and a.u is the iterate x.
       // ADMM: lds holds x(t) and a.u is the scaled dual u.
-      const float thr = a.thr;
+      const float thr = a.tau_dev ? a.tau_dev[a.t] * a.lam_dev[a.t] : a.thr;
       float2* st = reinterpret_cast<float2*>(a.u);
+      float l1_acc = 0.0f;   // objective trace: sum |x| of this thread's samples
 #pragma unroll
       for (int k0 = 0; k0 < EPT; k0 += CH) {
         float2 sv[CH];
@@ -378,13 +469,20 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
           const int i = tid + (k0 + k) * T;
           if (FULL || i < NE) {
             const size_t j = (size_t)(i / CB) * N2 + j2_0 + (i % CB);
-            if constexpr (MODE == B_ISTA) {
-              const float2 v = cadd(sv[k], lds[lp(i)]);
+            if constexpr (MODE == B_ISTA || MODE == B_ISTA_REC) {
+              const float2 step = lds[lp(i)];
+              const float2 v = cadd(sv[k], step);
               const float2 x = c2(soft(v.x, thr), soft(v.y, thr));
+              l1_acc += fabsf(x.x) + fabsf(x.y);
               st[j] = x;
               lds[lp(i)] = x;
+              if constexpr (MODE == B_ISTA_REC) {
+                reinterpret_cast<float2*>(a.rv)[j] = v;
+                reinterpret_cast<float2*>(a.rd)[j] = step;
+              }
             } else {
               const float2 x = lds[lp(i)];
+              l1_acc += fabsf(x.x) + fabsf(x.y);
               const float2 xu = cadd(x, sv[k]);
               const float2 z = c2(soft(xu.x, thr), soft(xu.y, thr));
               const float2 u1 = csub(xu, z);
@@ -399,7 +497,18 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
           }
         }
       }
+      if (a.l1) {
+        const double r = block_sum<T>(double(l1_acc), tid);
+        if (tid == 0) a.l1[blk] = r;
+      }
       fwd = !a.last;
+    } else if constexpr (MODE == B_ADJ_X) {
+      // xbar_{t-1} = vbar_t - tau_t A^T A vbar_t (lds holds the second term)
+      for (int i = tid; i < NE; i += T) {
+        const size_t j = (size_t)(i / CB) * N2 + j2_0 + (i % CB);
+        reinterpret_cast<float2*>(a.xbar)[j] = cadd(reinterpret_cast<const float2*>(a.vbar)[j], lds[lp(i)]);
+      }
+      fwd = false;
     } else if constexpr (MODE == B_OUT_ALL) {
       for (int i = tid; i < NE; i += T) {
         const int j1 = i / CB, c = i % CB;
@@ -417,6 +526,38 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
       fwd = false;
     }
     if (!fwd) return;
+    __syncthreads();
+  } else if constexpr (MODE == B_ADJ_V) {
+    // vbar_t = M_t * xbar_t with M_t = 1[|v_t| > theta_t]; per-workgroup sums
+    // of -sgn(v_t) vbar_t (threshold derivative) and vbar_t * step_t (the
+    // step's derivative, step_t = tau_t g_t), accumulated in double
+    const float thr = a.tau_dev[a.t] * a.lam_dev[a.t];
+    double s_th = 0.0, s_g = 0.0;
+    for (int i = tid; i < NE; i += T) {
+      const size_t j = (size_t)(i / CB) * N2 + j2_0 + (i % CB);
+      const float2 xb = reinterpret_cast<const float2*>(a.xbar)[j];
+      const float2 v = reinterpret_cast<const float2*>(a.rv)[j];
+      const float2 st = reinterpret_cast<const float2*>(a.rd)[j];
+      const float2 vb = c2(fabsf(v.x) > thr ? xb.x : 0.0f, fabsf(v.y) > thr ? xb.y : 0.0f);
+      s_th -= double(v.x > 0.0f ? vb.x : -vb.x) + double(v.y > 0.0f ? vb.y : -vb.y);
+      s_g += double(vb.x) * double(st.x) + double(vb.y) * double(st.y);
+      reinterpret_cast<float2*>(a.vbar)[j] = vb;
+      lds[lp(i)] = vb;
+    }
+    // workgroup reduction: wave sums by shuffles, then one value per wave
+    __shared__ double red[2][T / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+      s_th += __shfl_xor(s_th, off);
+      s_g += __shfl_xor(s_g, off);
+    }
+    if ((tid & 63) == 0) { red[0][tid >> 6] = s_th; red[1][tid >> 6] = s_g; }
+    __syncthreads();
+    if (tid == 0) {
+      double r0 = 0.0, r1 = 0.0;
+      for (int w = 0; w < T / 64; ++w) { r0 += red[0][w]; r1 += red[1][w]; }
+      a.part[0] = r0;
+      a.part[a.part_q] = r1;
+    }
     __syncthreads();
   } else {
 #pragma unroll

@@ -13,6 +13,14 @@ hipError_t launch_passA(int op, int d2, int grid, const PassAArgs& a, hipStream_
 template <int N1>
 hipError_t launch_passB(int mode, int grid, const PassBArgs& a, hipStream_t s);
 
+struct UStride;
+// batched (grid y = signal) row / column passes for the unrolled solver
+template <int N2>
+hipError_t launch_urow(int op, int d2, int grid, int batch, const PassAArgs& a, const UStride& st,
+                       hipStream_t s);
+template <int N1>
+hipError_t launch_ucol(int mode, int grid, int batch, const PassBArgs& a, const UStride& st, hipStream_t s);
+
 struct SolveArgs;
 // persistent solver for N = 2^LOGN complex points (inst_solve.hip)
 template <int LOGN>

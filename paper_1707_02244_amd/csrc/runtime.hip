@@ -23,6 +23,7 @@
 #include "launch.hpp"
 #include "solve_persistent.hpp"
 #include "batch.hpp"
+#include "unrolled.hpp"
 
 #include <algorithm>
 #include <numeric>
@@ -77,8 +78,11 @@ struct Plan {
   float2 *tw1 = nullptr, *tw2 = nullptr, *twlo = nullptr, *twhi = nullptr;
   float2 *twk1 = nullptr, *twp = nullptr;
   float* scal = nullptr;   // small device scalars (norm bound)
+  double* objbuf = nullptr; // objective-trace partial sums (grown on demand)
+  size_t obj_cap = 0;
   ~Plan() {
     if (mem) (void)hipFree(mem);
+    if (objbuf) (void)hipFree(objbuf);
   }
 };
 
@@ -255,6 +259,29 @@ hipError_t timed(int kind, hipStream_t s, F&& launch) {
   return hipSuccess;
 }
 
+hipError_t launchUA(const Plan& P, int op, int batch, const PassAArgs& a, const UStride& st, hipStream_t s) {
+  const int grid = P.N1 / 2;
+  const int d2 = P.d / 2;
+  switch (P.N2) {
+#define CS_CASE(L) case L: return launch_urow<L>(op, d2, grid, batch, a, st, s);
+    CS_CASE(16) CS_CASE(32) CS_CASE(64) CS_CASE(128) CS_CASE(256) CS_CASE(512) CS_CASE(1024)
+    CS_CASE(2048) CS_CASE(4096) CS_CASE(8192)
+#undef CS_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launchUB(const Plan& P, int mode, int batch, const PassBArgs& a, const UStride& st, hipStream_t s) {
+  const int grid = P.N2 / kColsPerBlock;
+  switch (P.N1) {
+#define CS_CASE(L) case L: return launch_ucol<L>(mode, grid, batch, a, st, s);
+    CS_CASE(8) CS_CASE(16) CS_CASE(32) CS_CASE(64) CS_CASE(128) CS_CASE(256) CS_CASE(512) CS_CASE(1024)
+    CS_CASE(2048)
+#undef CS_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
 PassAArgs argsA(const Plan& P) {
   PassAArgs a{};
   a.Y = P.Y; a.chat = P.chat; a.yhat = P.yhat; a.table = nullptr;
@@ -394,6 +421,136 @@ cs_status check_common(const void* c, int64_t n, int d) {
 
 bool finite(float v) { return std::isfinite(v); }
 
+// Gradients from the partial sums: block t adds the `count` partials of
+// step t (layout part[t][q][count]) in a fixed order and applies
+//   lambar_t = tau_t S0,  taubar_t = lam_t S0 + S1 / tau_t.
+__global__ void k_unrolled_grads(const double* __restrict__ part, int count, const float* __restrict__ tau,
+                                 const float* __restrict__ lam, float* __restrict__ g_lam,
+                                 float* __restrict__ g_tau) {
+  __shared__ double r0[256], r1[256];
+  const int t = blockIdx.x;
+  const double* p0 = part + (size_t)t * 2 * count;
+  const double* p1 = p0 + count;
+  double a0 = 0.0, a1 = 0.0;
+  for (int i = threadIdx.x; i < count; i += 256) { a0 += p0[i]; a1 += p1[i]; }
+  r0[threadIdx.x] = a0;
+  r1[threadIdx.x] = a1;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) { r0[threadIdx.x] += r0[threadIdx.x + k]; r1[threadIdx.x] += r1[threadIdx.x + k]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double tt = tau[t], ll = lam[t];
+    g_lam[t] = float(tt * r0[0]);
+    g_tau[t] = float(ll * r0[0] + r1[0] / tt);
+  }
+}
+
+// Objective trace: block t adds the row-pass residual partials res[t][*]
+// and the column-pass l1 partials l1[t][*] in a fixed order and writes
+//   obj[t] = 1/(2m) sum res + lambda sum l1    (Eq. 3 halved, Parseval)
+__global__ void k_objective(const double* __restrict__ res, int nres, const double* __restrict__ l1, int nl1,
+                            double inv_2m, double lambda, float* __restrict__ obj) {
+  __shared__ double r0[256], r1[256];
+  const int t = blockIdx.x;
+  const double* p0 = res + (size_t)t * nres;
+  const double* p1 = l1 + (size_t)t * nl1;
+  double a0 = 0.0, a1 = 0.0;
+  for (int i = threadIdx.x; i < nres; i += 256) a0 += p0[i];
+  for (int i = threadIdx.x; i < nl1; i += 256) a1 += p1[i];
+  r0[threadIdx.x] = a0;
+  r1[threadIdx.x] = a1;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) { r0[threadIdx.x] += r0[threadIdx.x + k]; r1[threadIdx.x] += r1[threadIdx.x + k]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) obj[t] = float(inv_2m * r0[0] + lambda * r1[0]);
+}
+
+// Partial-sum buffers of an objective trace over `iters` iterations:
+// res[iters][N1/2] (one per row-pass workgroup), then l1[iters][N2/8].
+cs_status get_objbuf(Plan& P, int iters, double** res, double** l1, hipStream_t s) {
+  const size_t nres = size_t(P.N1 / 2), nl1 = size_t(P.N2 / kColsPerBlock);
+  const size_t need = size_t(iters) * (nres + nl1);
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (P.obj_cap < need) {
+    CS_HIP(hipStreamSynchronize(s));
+    if (P.objbuf) CS_HIP(hipFree(P.objbuf));
+    P.objbuf = nullptr;
+    P.obj_cap = 0;
+    hipError_t e = hipMalloc(&P.objbuf, need * sizeof(double));
+    if (e != hipSuccess) return fail(CS_ENOMEM, "hipMalloc of %zu bytes for the objective trace failed",
+                                     need * sizeof(double));
+    P.obj_cap = need;
+  }
+  *res = P.objbuf;
+  *l1 = P.objbuf + size_t(iters) * nres;
+  return CS_OK;
+}
+
+// Unrolled ISTA workspace per (device, n, d, batch, checkpoint interval):
+// spectrum buffers, y_hat and ybar tables and time-domain state of every
+// signal, the records of one segment, and the partial sums (grown with K).
+struct UPlan {
+  float2 *Y = nullptr, *yhat = nullptr, *ybar = nullptr;
+  float *xs = nullptr, *rv = nullptr, *rd = nullptr, *xbar = nullptr, *vbar = nullptr;
+  double* part = nullptr;
+  size_t part_cap = 0;
+  void* mem = nullptr;
+};
+std::map<std::tuple<int, int64_t, int, int, int>, std::unique_ptr<UPlan>> g_uplans;
+
+int64_t ckpt_count(int K, int every) { return K > 0 ? (K - 1) / every : 0; }
+
+cs_status get_uplan(const Plan& P, int Bt, int every, int K, UPlan** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_tuple(P.dev, P.n, P.d, Bt, every);
+  auto& slot = g_uplans[key];
+  if (!slot) {
+    auto u = std::make_unique<UPlan>();
+    const size_t N = size_t(P.N), n = size_t(P.n), B = size_t(Bt), E = size_t(every);
+    const size_t bytes = (B * N + 2 * B * (N + 1)) * sizeof(float2) + (3 * B * n + 2 * E * B * n) * sizeof(float) + 1024;
+    hipError_t e = hipMalloc(&u->mem, bytes);
+    if (e != hipSuccess) return fail(CS_ENOMEM, "hipMalloc of %zu bytes for the unrolled workspace failed", bytes);
+    char* p = static_cast<char*>(u->mem);
+    auto take = [&](size_t b) { char* r = p; p += (b + 255) & ~size_t(255); return r; };
+    u->Y = reinterpret_cast<float2*>(take(B * N * sizeof(float2)));
+    u->yhat = reinterpret_cast<float2*>(take(B * (N + 1) * sizeof(float2)));
+    u->ybar = reinterpret_cast<float2*>(take(B * (N + 1) * sizeof(float2)));
+    u->xs = reinterpret_cast<float*>(take(B * n * sizeof(float)));
+    u->xbar = reinterpret_cast<float*>(take(B * n * sizeof(float)));
+    u->vbar = reinterpret_cast<float*>(take(B * n * sizeof(float)));
+    u->rv = reinterpret_cast<float*>(take(E * B * n * sizeof(float)));
+    u->rd = reinterpret_cast<float*>(take(E * B * n * sizeof(float)));
+    slot = std::move(u);
+  }
+  UPlan* u = slot.get();
+  const size_t need = size_t(K) * 2 * size_t(Bt) * size_t(P.N2 / kColsPerBlock);
+  if (u->part_cap < need) {
+    if (u->part) (void)hipFree(u->part);
+    u->part = nullptr;
+    u->part_cap = 0;
+    hipError_t e = hipMalloc(&u->part, need * sizeof(double));
+    if (e != hipSuccess) return fail(CS_ENOMEM, "hipMalloc of unrolled partial sums failed");
+    u->part_cap = need;
+  }
+  *out = u;
+  return CS_OK;
+}
+
+cs_status check_unrolled(const float* c, int64_t n, int d, int Bt, const float* y, const float* lam,
+                         const float* tau, int K, int every) {
+  cs_status st = check_common(c, n, d);
+  if (st != CS_OK) return st;
+  if (!y || !lam || !tau) return fail(CS_EINVAL, "y, lam or tau is NULL");
+  if (Bt < 1 || Bt > 65535) return fail(CS_EINVAL, "batch=%d must be in [1, 65535]", Bt);
+  if (K < 1) return fail(CS_EINVAL, "K=%d must be >= 1", K);
+  if (every < 1) return fail(CS_EINVAL, "every=%d must be >= 1", every);
+  return CS_OK;
+}
+
 }  // namespace
 }  // namespace cs
 
@@ -508,6 +665,155 @@ cs_status cs_ista_solve_batched(int32_t count, const int64_t* n_host, int32_t d,
   BatchSig* dsig = B.sigs;
   unsigned* q = B.queue;
   CS_LAUNCH(timed(T_BATCH, s, [&] { return launch_batch_dispatch(d / 2, dsig, count, q, iters, grid, s); }));
+  g_err.clear();
+  return CS_OK;
+}
+
+size_t cs_unrolled_ckpt_bytes(int64_t n, int32_t d, int32_t Bt, int32_t K, int32_t every) {
+  (void)d;
+  if (n <= 0 || Bt <= 0 || K <= 0 || every <= 0) return 0;
+  return size_t(ckpt_count(K, every)) * size_t(Bt) * size_t(n) * sizeof(float);
+}
+
+cs_status cs_unrolled_ista_fwd(const float* c, int64_t n, int32_t d, int32_t Bt, const float* y, const float* lam,
+                               const float* tau, int32_t K, int32_t every, float* xK, void* ckpt,
+                               cs_stream stream) {
+  cs_status st = check_unrolled(c, n, d, Bt, y, lam, tau, K, every);
+  if (st != CS_OK) return st;
+  if (!xK) return fail(CS_EINVAL, "xK is NULL");
+  if (ckpt_count(K, every) > 0 && !ckpt) return fail(CS_EINVAL, "ckpt is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Plan* P = nullptr;
+  if ((st = get_plan(n, d, &P)) != CS_OK) return st;
+  UPlan* U = nullptr;
+  if ((st = get_uplan(*P, Bt, every, K, &U)) != CS_OK) return st;
+  const int64_t N = P->N, m = n / d;
+  if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
+  // per-signal y_hat tables
+  UStride us{};
+  us.Y = N; us.yhat = N + 1; us.table = N + 1; us.in0 = m; us.u = n; us.out0 = m;
+  us.rv = n; us.rd = n; us.xbar = n; us.vbar = n; us.part = P->N2 / kColsPerBlock;
+  {
+    PassBArgs b = argsB(*P);
+    b.Y = U->Y;
+    b.in0 = y;
+    CS_LAUNCH(launchUB(*P, B_FWD_UP, Bt, b, us, s));
+    PassAArgs a = argsA(*P);
+    a.Y = U->Y;
+    a.table = U->yhat;
+    CS_LAUNCH(launchUA(*P, A_SPEC, Bt, a, us, s));
+  }
+  if ((st = fill(reinterpret_cast<float*>(U->Y), size_t(Bt) * size_t(N) * 2, 0.0f, s)) != CS_OK) return st;
+  if ((st = fill(xK, size_t(Bt) * size_t(n), 0.0f, s)) != CS_OK) return st;
+  PassAArgs a = argsA(*P);
+  a.Y = U->Y; a.yhat = U->yhat; a.tau_dev = tau;
+  PassBArgs b = argsB(*P);
+  b.Y = U->Y; b.u = xK; b.tau_dev = tau; b.lam_dev = lam;
+  for (int t = 0; t < K; ++t) {
+    a.t = t;
+    CS_LAUNCH(launchUA(*P, A_ISTA, Bt, a, us, s));
+    b.t = t;
+    b.last = (t == K - 1);
+    CS_LAUNCH(launchUB(*P, B_ISTA, Bt, b, us, s));
+    if ((t + 1) % every == 0 && t + 1 < K) {
+      float* dst = static_cast<float*>(ckpt) + size_t((t + 1) / every - 1) * size_t(Bt) * size_t(n);
+      CS_HIP(hipMemcpyAsync(dst, xK, size_t(Bt) * size_t(n) * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+  }
+  g_err.clear();
+  return CS_OK;
+}
+
+cs_status cs_unrolled_ista_bwd(const float* c, int64_t n, int32_t d, int32_t Bt, const float* y, const float* lam,
+                               const float* tau, int32_t K, int32_t every, const void* ckpt, const float* g_xK,
+                               float* g_lam, float* g_tau, float* g_y, cs_stream stream) {
+  cs_status st = check_unrolled(c, n, d, Bt, y, lam, tau, K, every);
+  if (st != CS_OK) return st;
+  if (!g_xK || !g_lam || !g_tau || !g_y) return fail(CS_EINVAL, "a gradient pointer is NULL");
+  if (ckpt_count(K, every) > 0 && !ckpt) return fail(CS_EINVAL, "ckpt is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Plan* P = nullptr;
+  if ((st = get_plan(n, d, &P)) != CS_OK) return st;
+  UPlan* U = nullptr;
+  if ((st = get_uplan(*P, Bt, every, K, &U)) != CS_OK) return st;
+  const int64_t N = P->N, m = n / d;
+  const int nblk = P->N2 / kColsPerBlock;
+  const size_t BN = size_t(Bt) * size_t(n);
+  if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
+  UStride us{};
+  us.Y = N; us.yhat = N + 1; us.ybar = N + 1; us.table = N + 1; us.in0 = 0; us.u = n; us.out0 = m;
+  us.rv = n; us.rd = n; us.xbar = n; us.vbar = n; us.part = nblk;
+  {
+    UStride uy = us;
+    uy.in0 = m;
+    PassBArgs b = argsB(*P);
+    b.Y = U->Y;
+    b.in0 = y;
+    CS_LAUNCH(launchUB(*P, B_FWD_UP, Bt, b, uy, s));
+    PassAArgs a = argsA(*P);
+    a.Y = U->Y;
+    a.table = U->yhat;
+    CS_LAUNCH(launchUA(*P, A_SPEC, Bt, a, us, s));
+  }
+  if ((st = fill(reinterpret_cast<float*>(U->ybar), size_t(Bt) * size_t(N + 1) * 2, 0.0f, s)) != CS_OK) return st;
+  CS_HIP(hipMemcpyAsync(U->xbar, g_xK, BN * sizeof(float), hipMemcpyDeviceToDevice, s));
+  const int nseg = (K + every - 1) / every;
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int t0 = sg * every, t1 = std::min(K, t0 + every);
+    // x_{t0}: zero or the checkpoint; its spectrum into Y
+    if (sg == 0) {
+      if ((st = fill(U->xs, BN, 0.0f, s)) != CS_OK) return st;
+    } else {
+      const float* src = static_cast<const float*>(ckpt) + size_t(sg - 1) * BN;
+      CS_HIP(hipMemcpyAsync(U->xs, src, BN * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+    {
+      UStride ux = us;
+      ux.in0 = n;
+      PassBArgs b = argsB(*P);
+      b.Y = U->Y;
+      b.in0 = U->xs;
+      CS_LAUNCH(launchUB(*P, B_FWD_REAL, Bt, b, ux, s));
+    }
+    // recompute the segment, recording v_t and the step
+    for (int t = t0; t < t1; ++t) {
+      PassAArgs a = argsA(*P);
+      a.Y = U->Y; a.yhat = U->yhat; a.tau_dev = tau; a.t = t;
+      CS_LAUNCH(launchUA(*P, A_ISTA, Bt, a, us, s));
+      PassBArgs b = argsB(*P);
+      b.Y = U->Y; b.u = U->xs; b.tau_dev = tau; b.lam_dev = lam; b.t = t; b.last = (t == t1 - 1);
+      b.rv = U->rv + size_t(t - t0) * BN;
+      b.rd = U->rd + size_t(t - t0) * BN;
+      CS_LAUNCH(launchUB(*P, B_ISTA_REC, Bt, b, us, s));
+    }
+    // reverse through the segment
+    for (int t = t1 - 1; t >= t0; --t) {
+      PassBArgs b = argsB(*P);
+      b.Y = U->Y; b.xbar = U->xbar; b.vbar = U->vbar; b.tau_dev = tau; b.lam_dev = lam; b.t = t;
+      b.rv = U->rv + size_t(t - t0) * BN;
+      b.rd = U->rd + size_t(t - t0) * BN;
+      b.part = U->part + size_t(t) * 2 * size_t(Bt) * size_t(nblk);
+      b.part_q = Bt * nblk;
+      CS_LAUNCH(launchUB(*P, B_ADJ_V, Bt, b, us, s));
+      PassAArgs a = argsA(*P);
+      a.Y = U->Y; a.ybar = U->ybar; a.tau_dev = tau; a.t = t;
+      CS_LAUNCH(launchUA(*P, A_ADJ, Bt, a, us, s));
+      PassBArgs bx = argsB(*P);
+      bx.Y = U->Y; bx.xbar = U->xbar; bx.vbar = U->vbar;
+      CS_LAUNCH(launchUB(*P, B_ADJ_X, Bt, bx, us, s));
+    }
+  }
+  k_unrolled_grads<<<dim3(K), dim3(256), 0, s>>>(U->part, Bt * nblk, tau, lam, g_lam, g_tau);
+  CS_HIP(hipGetLastError());
+  // ybar = IDFT_m of the accumulated spectrum: tile onto n bins, inverse, decimate
+  {
+    PassAArgs a = argsA(*P);
+    a.Y = U->Y; a.ybar = U->ybar;
+    CS_LAUNCH(launchUA(*P, A_TILE, Bt, a, us, s));
+    PassBArgs b = argsB(*P);
+    b.Y = U->Y; b.out0 = g_y;
+    CS_LAUNCH(launchUB(*P, B_OUT_DEC, Bt, b, us, s));
+  }
   g_err.clear();
   return CS_OK;
 }
@@ -645,7 +951,6 @@ cs_status cs_ista_solve(const float* c, int64_t n, int32_t d, const float* y, fl
   if (!finite(lambda) || lambda < 0.0f) return fail(CS_EINVAL, "lambda=%g must be finite and >= 0", lambda);
   if (!finite(tau) || tau <= 0.0f) return fail(CS_EINVAL, "tau=%g must be finite and > 0", tau);
   if (iters < 0) return fail(CS_EINVAL, "iters=%d must be >= 0", iters);
-  if (obj) return fail(CS_ENOTSUP, "objective trace is not supported; pass obj = NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (iters == 0) {
     if ((st = fill(x, size_t(n), 0.0f, s)) != CS_OK) return st;
@@ -657,7 +962,7 @@ cs_status cs_ista_solve(const float* c, int64_t n, int32_t d, const float* y, fl
   if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
   if ((st = setup_yhat(*P, y, s)) != CS_OK) return st;
   bool pers = false;
-  if ((st = use_persistent(*P, 0, &pers)) != CS_OK) return st;
+  if (!obj && (st = use_persistent(*P, 0, &pers)) != CS_OK) return st;
   if (pers) {
     // counter and error flag start at zero (bit pattern of 0.0f)
     if ((st = fill(reinterpret_cast<float*>(P->bar), 1, 0.0f, s)) != CS_OK) return st;
@@ -672,15 +977,28 @@ cs_status cs_ista_solve(const float* c, int64_t n, int32_t d, const float* y, fl
   }
   if ((st = fill(reinterpret_cast<float*>(P->Y), size_t(P->N) * 2, 0.0f, s)) != CS_OK) return st;
   if ((st = fill(x, size_t(n), 0.0f, s)) != CS_OK) return st;
+  double *res = nullptr, *l1 = nullptr;
+  if (obj && (st = get_objbuf(*P, iters, &res, &l1, s)) != CS_OK) return st;
+  const int nres = P->N1 / 2, nl1 = P->N2 / kColsPerBlock;
   PassAArgs a = argsA(*P);
   a.tau = tau;
   PassBArgs b = argsB(*P);
   b.thr = tau * lambda;
   b.u = x;
+  // objective trace: obj[t-1] = F(x(t)); the row pass of iteration t + 1
+  // sees x(t)'s spectrum, and one residual-only row pass follows the loop
   for (int t = 1; t <= iters; ++t) {
+    a.res = (obj && t >= 2) ? res + size_t(t - 2) * nres : nullptr;
     CS_LAUNCH(timed(T_A_ISTA, s, [&] { return launchA(*P, A_ISTA, a, s); }));
-    b.last = (t == iters);
+    b.last = (t == iters) && !obj;
+    b.l1 = obj ? l1 + size_t(t - 1) * nl1 : nullptr;
     CS_LAUNCH(timed(T_B_ISTA, s, [&] { return launchB(*P, B_ISTA, b, s); }));
+  }
+  if (obj) {
+    a.res = res + size_t(iters - 1) * nres;
+    CS_LAUNCH(launchA(*P, A_RES, a, s));
+    k_objective<<<dim3(iters), dim3(256), 0, s>>>(res, nres, l1, nl1, 0.5 / double(n / d), double(lambda), obj);
+    CS_HIP(hipGetLastError());
   }
   g_err.clear();
   return CS_OK;
@@ -695,7 +1013,6 @@ cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, fl
   if (!finite(lambda) || lambda < 0.0f) return fail(CS_EINVAL, "lambda=%g must be finite and >= 0", lambda);
   if (!finite(rho) || rho <= 0.0f) return fail(CS_EINVAL, "rho=%g must be finite and > 0", rho);
   if (iters < 0) return fail(CS_EINVAL, "iters=%d must be >= 0", iters);
-  if (obj) return fail(CS_ENOTSUP, "objective trace is not supported; pass obj = NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (iters == 0) {
     if (!warm) {
@@ -711,7 +1028,7 @@ cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, fl
   if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
   if ((st = setup_yhat(*P, y, s)) != CS_OK) return st;
   bool pers = false;
-  if ((st = use_persistent(*P, 1, &pers)) != CS_OK) return st;
+  if (!obj && (st = use_persistent(*P, 1, &pers)) != CS_OK) return st;
   if (pers) {
     if ((st = fill(reinterpret_cast<float*>(P->bar), 1, 0.0f, s)) != CS_OK) return st;
     SolveArgs sa = solve_args(*P);
@@ -744,10 +1061,20 @@ cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, fl
   b.out0 = x;
   b.out1 = z;
   b.u = u;
+  double *res = nullptr, *l1 = nullptr;
+  if (obj && (st = get_objbuf(*P, iters, &res, &l1, s)) != CS_OK) return st;
+  const int nres = P->N1 / 2, nl1 = P->N2 / kColsPerBlock;
+  // objective trace: obj[t-1] = F(x(t)), both parts from iteration t
   for (int t = 1; t <= iters; ++t) {
+    a.res = obj ? res + size_t(t - 1) * nres : nullptr;
     CS_LAUNCH(timed(T_A_ADMM, s, [&] { return launchA(*P, A_ADMM, a, s); }));
     b.last = (t == iters);
+    b.l1 = obj ? l1 + size_t(t - 1) * nl1 : nullptr;
     CS_LAUNCH(timed(T_B_ADMM, s, [&] { return launchB(*P, B_ADMM, b, s); }));
+  }
+  if (obj) {
+    k_objective<<<dim3(iters), dim3(256), 0, s>>>(res, nres, l1, nl1, 0.5 / double(n / d), double(lambda), obj);
+    CS_HIP(hipGetLastError());
   }
   g_err.clear();
   return CS_OK;

@@ -1,0 +1,70 @@
+// Unrolled ISTA over a batch of signals that share one sensing operator:
+// forward with per-iteration parameters and a checkpointed reverse pass.
+//
+// The row and column passes of kernels.hpp run with a second grid dimension
+// over the signals of the batch; each signal has its own spectrum buffer,
+// y_hat table, state and records, found by per-signal strides (c_hat is
+// shared).  The reverse pass is the adjoint of the recursion
+//     v_t = x_{t-1} + tau_t A^T (y - A x_{t-1}),  x_t = eta_{tau_t lam_t}(v_t):
+//     vbar_t = M_t xbar_t,  M_t = 1[|v_t| > tau_t lam_t]
+//     d theta_t = -sum sgn(v_t) vbar_t,  lambar_t = tau_t d theta_t,
+//     taubar_t = lam_t d theta_t + sum vbar_t g_t,
+//     ybar += tau_t A vbar_t,  xbar_{t-1} = vbar_t - tau_t A^T A vbar_t.
+// A vbar_t is accumulated in the m-point spectral domain (row pass A_ADJ) and
+// brought back to the time domain once at the end (A_TILE + decimation).
+#pragma once
+#include "kernels.hpp"
+
+namespace cs {
+
+// Per-signal strides, in elements of each buffer's type (0: shared).
+struct UStride {
+  long long Y;      // row and column pass spectrum buffer (float2)
+  long long yhat;   // y_hat table (float2)
+  long long ybar;   // ybar spectrum (float2)
+  long long table;  // A_SPEC destination (float2)
+  long long in0;    // column-pass input (float)
+  long long u;      // column-pass state (float)
+  long long out0;   // column-pass output (float)
+  long long rv, rd, xbar, vbar;   // records and adjoint state (float)
+  long long part;   // partial sums (double): per signal, then + blockIdx.x
+};
+
+template <int N2, int OP, int D2>
+__global__ __launch_bounds__(kThreads) void k_urow(PassAArgs a, UStride st) {
+  constexpr int LD = N2 + kPadA;
+  constexpr bool TW_LDS = (lds_padded(2 * LD) + N2) * 8 <= 160 * 1024 - 1024;
+  __shared__ float2 lds[lds_padded(2 * LD)];
+  __shared__ float2 tws_l[TW_LDS ? N2 : 1];
+  const long long b = blockIdx.y;
+  a.Y += b * st.Y;
+  if (a.yhat) a.yhat += b * st.yhat;
+  if (a.ybar) a.ybar += b * st.ybar;
+  if (a.table) a.table += b * st.table;
+  if constexpr (TW_LDS) {
+    for (unsigned i = threadIdx.x; i < N2; i += kThreads) tws_l[i] = a.tw2[i];
+  }
+  __syncthreads();
+  rowpass<N2, OP, D2, kThreads>(a, blockIdx.x, lds, TW_LDS ? tws_l : a.tw2, threadIdx.x);
+}
+
+template <int N1, int MODE>
+__global__ __launch_bounds__(kThreads) void k_ucol(PassBArgs a, UStride st) {
+  __shared__ float2 lds[lds_padded(N1 * kColsPerBlock)];
+  __shared__ float2 tws[N1];
+  const long long b = blockIdx.y;
+  a.Y += b * st.Y;
+  if (a.in0) a.in0 += b * st.in0;
+  if (a.u) a.u += b * st.u;
+  if (a.out0) a.out0 += b * st.out0;
+  if (a.rv) a.rv += b * st.rv;
+  if (a.rd) a.rd += b * st.rd;
+  if (a.xbar) a.xbar += b * st.xbar;
+  if (a.vbar) a.vbar += b * st.vbar;
+  if (a.part) a.part += b * st.part + blockIdx.x;
+  for (unsigned i = threadIdx.x; i < N1; i += kThreads) tws[i] = a.tw1[i];
+  __syncthreads();
+  colpass<N1, MODE, kThreads>(a, blockIdx.x, lds, tws, threadIdx.x);
+}
+
+}  // namespace cs

@@ -74,10 +74,12 @@ def test_bad_admm_scalars_rejected(lam, rho, iters):
     assert lib.cs_admm_solve(FAKE, 4096, 4, FAKE, lam, rho, iters, 0, FAKE, FAKE, FAKE, NULL, NULL) == _lib.CS_EINVAL
 
 
-def test_objective_trace_not_supported():
+def test_objective_trace_arguments_checked_first():
+    """With a trace requested, argument errors are still reported before any
+    device work."""
     lib = cs.load()
-    assert lib.cs_ista_solve(FAKE, 4096, 4, FAKE, 0.1, 0.1, 5, FAKE, FAKE, NULL) == _lib.CS_ENOTSUP
-    assert lib.cs_admm_solve(FAKE, 4096, 4, FAKE, 0.1, 1.0, 5, 0, FAKE, FAKE, FAKE, FAKE, NULL) == _lib.CS_ENOTSUP
+    assert lib.cs_ista_solve(FAKE, 4096, 4, FAKE, 0.1, 0.1, -1, FAKE, FAKE, NULL) == _lib.CS_EINVAL
+    assert lib.cs_admm_solve(FAKE, 4096, 4, FAKE, 0.1, -1.0, 5, 0, FAKE, FAKE, FAKE, FAKE, NULL) == _lib.CS_EINVAL
 
 
 def test_timing_read_unknown_name():

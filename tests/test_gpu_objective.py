@@ -1,0 +1,151 @@
+"""GPU objective trace (Eq. 3 halved, Parseval residual from the iteration's
+own spectrum) against the FP64 oracle's objective of the oracle's iterates.
+
+Tolerance: relative 1e-5 per entry, the bar of the final-objective check;
+both the FP32 spectral residual and the iterate differences (<= 1e-4 in l2,
+entering F to first order through a gradient that vanishes at the optimum)
+stay well inside it on these workloads."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import dense, fftref, problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1707_02244_amd as cs  # noqa: E402
+
+DEV = torch.device("cuda:0")
+F_TOL = 1e-5
+
+
+def g(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def h(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    pr = problem.build(workloads.cfg1())
+    return pr, pr.A()
+
+
+def trace(n):
+    return torch.empty(n, device=DEV, dtype=torch.float32)
+
+
+def test_ista_trace_cfg1(cfg1):
+    pr, A = cfg1
+    y = pr.y.astype(np.float64)
+    lam, tau = float(pr.lam), float(pr.tau)
+    T = workloads.CFG1_PARAMS["ista_iters"]
+    _, hist = dense.ista(A, y, lam, tau, T, record=True)
+    ref = np.array([dense.objective(A, y, lam, x) for x in hist])
+    obj = trace(T)
+    x = cs.ista_solve(g(pr.c), pr.d, g(pr.y), pr.lam, pr.tau, T, obj=obj)
+    got = h(obj)
+    err = np.abs(got - ref) / ref
+    print("ista trace cfg1: worst rel err %.2e (t=%d)" % (err.max(), err.argmax() + 1))
+    assert err.max() <= F_TOL
+    # the last entry is the objective of the returned iterate
+    assert abs(got[-1] - dense.objective(A, y, lam, h(x))) <= F_TOL * ref[-1]
+
+
+def test_ista_trace_is_monotone(cfg1):
+    """tau <= 1/||A||^2: ISTA cannot increase the objective; FP32 may only
+    wobble at the level of its round-off once the iterates stall."""
+    pr, _ = cfg1
+    T = workloads.CFG1_PARAMS["ista_iters"]
+    obj = trace(T)
+    cs.ista_solve(g(pr.c), pr.d, g(pr.y), pr.lam, pr.tau, T, obj=obj)
+    f = h(obj)
+    assert np.all(np.diff(f) <= 2e-6 * f[:-1])
+    assert f[-1] < 0.5 * float(pr.y.astype(np.float64) @ pr.y.astype(np.float64))
+
+
+def test_admm_trace_cfg1(cfg1):
+    pr, A = cfg1
+    y = pr.y.astype(np.float64)
+    lam = float(pr.lam)
+    rho = workloads.CFG1_PARAMS["rho"]
+    T = workloads.CFG1_PARAMS["admm_iters"]
+    _, hist = dense.admm(A, y, lam, rho, T, record=True)
+    ref = np.array([dense.objective(A, y, lam, rec[0]) for rec in hist])
+    obj = trace(T)
+    cs.admm_solve(g(pr.c), pr.d, g(pr.y), pr.lam, rho, T, obj=obj)
+    got = h(obj)
+    err = np.abs(got - ref) / ref
+    print("admm trace cfg1: worst rel err %.2e (t=%d)" % (err.max(), err.argmax() + 1))
+    assert err.max() <= F_TOL
+
+
+@pytest.mark.parametrize("n,d,k", [(256, 2, 4), (512, 16, 3), (8192, 8, 60)])
+def test_trace_other_shapes(n, d, k):
+    pr = problem.build(workloads.signal(n, d, k, 900 + n))
+    A = pr.A()
+    y = pr.y.astype(np.float64)
+    lam, tau = float(pr.lam), float(pr.tau)
+    T = 60
+    _, hi = dense.ista(A, y, lam, tau, T, record=True)
+    _, ha = dense.admm(A, y, lam, 0.5, T, record=True)
+    oi, oa = trace(T), trace(T)
+    cs.ista_solve(g(pr.c), d, g(pr.y), pr.lam, pr.tau, T, obj=oi)
+    cs.admm_solve(g(pr.c), d, g(pr.y), pr.lam, 0.5, T, obj=oa)
+    ri = np.array([dense.objective(A, y, lam, x) for x in hi])
+    ra = np.array([dense.objective(A, y, lam, r[0]) for r in ha])
+    assert np.max(np.abs(h(oi) - ri) / ri) <= F_TOL
+    assert np.max(np.abs(h(oa) - ra) / ra) <= F_TOL
+
+
+def test_trace_does_not_change_the_iterates(cfg1):
+    """A trace switches to the two-launch schedule and adds reductions only:
+    the iterates equal those of the two-launch schedule without a trace."""
+    pr, _ = cfg1
+    c, yg = g(pr.c), g(pr.y)
+    cs.set_solver_path(cs.PATH_TWO_PASS)
+    try:
+        x0 = h(cs.ista_solve(c, pr.d, yg, pr.lam, pr.tau, 50))
+        a0 = [h(v) for v in cs.admm_solve(c, pr.d, yg, pr.lam, 1.0, 30)]
+    finally:
+        cs.set_solver_path(cs.PATH_AUTO)
+    x1 = h(cs.ista_solve(c, pr.d, yg, pr.lam, pr.tau, 50, obj=trace(50)))
+    a1 = [h(v) for v in cs.admm_solve(c, pr.d, yg, pr.lam, 1.0, 30, obj=trace(30))]
+    assert np.array_equal(x0, x1)
+    assert all(np.array_equal(p, q) for p, q in zip(a0, a1))
+
+
+def test_trace_flags_non_finite_input(cfg1):
+    """A NaN in y reaches the trace (the divergence guard a caller reads)."""
+    pr, _ = cfg1
+    y = pr.y.copy()
+    y[7] = np.nan
+    obj = trace(5)
+    cs.ista_solve(g(pr.c), pr.d, g(y), pr.lam, pr.tau, 5, obj=obj)
+    assert np.all(np.isnan(h(obj)))
+
+
+def test_trace_full_size():
+    """n = 2^22, d = 4: the first entries against the oracle's iterates, and
+    the last entry against the oracle's FP64 objective of the returned x."""
+    pr = problem.build(workloads.cfg2())
+    op = pr.op()
+    y = pr.y.astype(np.float64)
+    lam, tau = float(pr.lam), float(pr.tau)
+    _, hist = fftref.ista(op, y, lam, tau, 3, record=True)
+    T = workloads.CFG2_PARAMS["ista_iters"]
+    obj = trace(T)
+    x = cs.ista_solve(g(pr.c), pr.d, g(pr.y), pr.lam, pr.tau, T, obj=obj)
+    got = h(obj)
+    for t in (1, 2, 3):
+        ref = fftref.objective(op, y, lam, hist[t - 1][1])
+        assert abs(got[t - 1] - ref) <= F_TOL * ref, t
+    ref = fftref.objective(op, y, lam, h(x))
+    assert abs(got[-1] - ref) <= F_TOL * ref

@@ -121,3 +121,20 @@ def test_planted_adjoint_mistakes_are_caught(mut):
     ok = all(np.max(np.abs(a - b)) <= 1e-10 * max(np.max(np.abs(b)), 1e-30)
              for a, b in ((gl, rl), (gt, rt), (gy, ry)))
     assert not ok
+
+
+def test_flipping_a_decided_mask_changes_the_gradients():
+    """The mask override is live: flipping an entry far from its kink changes
+    the gradients, and flipping nothing changes nothing."""
+    K = 12
+    op, Y, Xs, lam, tau = setup(64, 4, 2, 3, 5, K)
+    base = unrolled.backward(op, Y, lam, tau, K, Xs)
+    same = unrolled.backward(op, Y, lam, tau, K, Xs, flip=[])
+    assert all(np.array_equal(a, b) for a, b in zip(base, same))
+    _, rec = unrolled.forward(op, Y, lam, tau, K)
+    V = rec[K - 1][2]
+    b, i = np.unravel_index(np.argmax(np.abs(V)), V.shape)
+    moved = unrolled.backward(op, Y, lam, tau, K, Xs, flip=[(K - 1, int(b), int(i))])
+    assert not np.allclose(moved[0], base[0])
+    amb = unrolled.ambiguous(op, Y, lam, tau, K, 1e300)
+    assert len(amb) == K * Y.shape[0] * op.n
