@@ -135,6 +135,46 @@ cs_status cs_unrolled_ista_bwd(const float* c, int64_t n, int32_t d, int32_t Bt,
                                const float* tau, int32_t K, int32_t every, const void* ckpt, const float* g_xK,
                                float* g_lam, float* g_tau, float* g_y, cs_stream stream);
 
+/* ---- 2-D sensing with a blur --------------------------------------------
+ * An image x of `rows` x `cols` pixels (row-major; both powers of two,
+ * 16 <= rows <= 8192, 16 <= cols <= 4096) is blurred by a point-spread
+ * function h and sensed by a 2-D kernel s, both by periodic 2-D convolution
+ * ((K x)[i][j] = sum_{a,b} k[(i-a) mod rows][(j-b) mod cols] x[a][b]), then
+ * decimated to the pixels (2i, 2j):
+ *     y = A x = P C H x,   y: rows/2 x cols/2 (row-major).
+ * The blur as one more circulant factor is how Section 7 casts deblurring;
+ * C H is doubly block circulant, so the 2-D DFT diagonalises it with
+ * eigenvalues DFT2(s) * DFT2(h), and A A^T is the (rows/2 x cols/2) doubly
+ * block circulant with eigenvalues the 2x2 alias averages of their squared
+ * magnitudes.  s and h are rows x cols device arrays; h may be NULL (no
+ * blur).  The decimation is 2 along both axes.  A plan per (device, rows,
+ * cols) holds about 2.5 rows*cols complex values of workspace (kept), and
+ * every call recomputes DFT2(s) DFT2(h) and (solvers) DFT2(y) on the
+ * stream.  Same conventions as above otherwise.  */
+cs_status cs2_apply(const float* s, const float* h, int32_t rows, int32_t cols, const float* x, float* y,
+                    cs_stream stream);
+/* x = A^T r = H^T C^T P^T r.  r: rows/2 x cols/2, x: rows x cols.  */
+cs_status cs2_apply_T(const float* s, const float* h, int32_t rows, int32_t cols, const float* r, float* x,
+                      cs_stream stream);
+/* max |DFT2(s) DFT2(h)|^2 written to out[0] (device): an upper bound on
+ * ||A||_2^2, so tau = 1/out is an admissible ISTA step.  */
+cs_status cs2_norm_bound(const float* s, const float* h, int32_t rows, int32_t cols, float* out,
+                         cs_stream stream);
+/* ISTA (Alg. 1) on the 2-D operator, as cs_ista_solve: x(0) = 0,
+ * x(t) = eta_{tau lambda}(x(t-1) + tau A^T (y - A x(t-1))).  x: rows x cols
+ * output; obj: NULL or `iters` floats, obj[t-1] = F(x(t)).  */
+cs_status cs2_ista_solve(const float* s, const float* h, int32_t rows, int32_t cols, const float* y, float lambda,
+                         float tau, int32_t iters, float* x, float* obj, cs_stream stream);
+/* ADMM (Alg. 2) on the 2-D operator, as cs_admm_solve (same x, z, u, warm
+ * and obj semantics).  The x-update applies (A^T A + rho I)^{-1} exactly in
+ * the Fourier domain, in the residual form
+ *     X' = W + conj(g_hat) (Y_hat - S_W) / (rho + Lam),
+ * W = DFT2(z - u), S_W the 2x2-folded g_hat W: equal to the Woodbury
+ * form, but without its cancellation when Lam >> rho.  */
+cs_status cs2_admm_solve(const float* s, const float* h, int32_t rows, int32_t cols, const float* y, float lambda,
+                         float rho, int32_t iters, int32_t warm, float* x, float* z, float* u, float* obj,
+                         cs_stream stream);
+
 /* Solver schedule.  For 2^8 <= n <= 2^22 a solve runs as ONE cooperative
  * launch: all iterations in a persistent kernel whose workgroups keep the
  * time-domain state in registers and meet at a grid barrier between the row
@@ -153,8 +193,9 @@ cs_status cs_check_device(cs_stream stream);
  * of the solvers' per-iteration kernels (or persistent solve kernel) is bracketed by a pair of
  * hipEvents recorded on the caller's stream.  cs_timing_read waits for the
  * recorded launches of one kernel ("passA_ista", "passB_ista", "passA_admm",
- * "passB_admm", the persistent "solve_ista", "solve_admm", or the batched
- * "batch_ista"), returns their count and summed duration in milliseconds,
+ * "passB_admm", the persistent "solve_ista", "solve_admm", the batched
+ * "batch_ista", or the 2-D "col2_ista", "row2_ista", "col2_admm",
+ * "row2_admm"), returns their count and summed duration in milliseconds,
  * and forgets them.  Timing adds event records to the stream; leave it off
  * for production runs.  */
 cs_status cs_timing_enable(int32_t on);

@@ -18,7 +18,8 @@ _NAMES = {CS_EINVAL: "CS_EINVAL", CS_ENOMEM: "CS_ENOMEM", CS_EHIP: "CS_EHIP", CS
 
 EXPORTS = ["cs_circ_apply", "cs_circ_apply_T", "cs_circ_norm_bound", "cs_ista_solve",
            "cs_admm_solve", "cs_ista_solve_batched", "cs_unrolled_ckpt_bytes", "cs_unrolled_ista_fwd",
-           "cs_unrolled_ista_bwd", "cs_set_solver_path", "cs_check_device", "cs_timing_enable",
+           "cs_unrolled_ista_bwd", "cs2_apply", "cs2_apply_T", "cs2_norm_bound", "cs2_ista_solve",
+           "cs2_admm_solve", "cs_set_solver_path", "cs_check_device", "cs_timing_enable",
            "cs_timing_read", "cs_last_error", "cs_version"]
 
 
@@ -51,6 +52,11 @@ def load():
         "cs_unrolled_ckpt_bytes": [I64, I32, I32, I32, I32],
         "cs_unrolled_ista_fwd": [P, I64, I32, I32, P, P, P, I32, I32, P, P, P],
         "cs_unrolled_ista_bwd": [P, I64, I32, I32, P, P, P, I32, I32, P, P, P, P, P, P],
+        "cs2_apply": [P, P, I32, I32, P, P, P],
+        "cs2_apply_T": [P, P, I32, I32, P, P, P],
+        "cs2_norm_bound": [P, P, I32, I32, P, P],
+        "cs2_ista_solve": [P, P, I32, I32, P, F, F, I32, P, P, P],
+        "cs2_admm_solve": [P, P, I32, I32, P, F, F, I32, I32, P, P, P, P, P],
         "cs_set_solver_path": [I32],
         "cs_check_device": [P],
         "cs_timing_enable": [I32],
@@ -146,6 +152,70 @@ def admm_solve(c, d, y, lam, rho, iters, x=None, z=None, u=None, warm=False, obj
     _check(load().cs_admm_solve(_ptr(c, "c"), n, d, _ptr(y, "y", n // d), float(lam), float(rho),
                                 int(iters), int(bool(warm)), _ptr(x, "x", n), _ptr(z, "z", n),
                                 _ptr(u, "u", n), _ptr(obj, "obj", iters), _stream(c)))
+    return x, z, u
+
+
+def _shape2(s):
+    if s.dim() != 2:
+        raise ValueError("s must be a 2-D (rows x cols) tensor")
+    return int(s.shape[0]), int(s.shape[1])
+
+
+def apply2(s, h, x, y=None):
+    """y = P C H x on a rows x cols image (h may be None); y is rows/2 x cols/2."""
+    import torch
+    R, C = _shape2(s)
+    if y is None:
+        y = torch.empty(R // 2, C // 2, device=s.device, dtype=torch.float32)
+    _check(load().cs2_apply(_ptr(s, "s"), _ptr(h, "h", R * C), R, C, _ptr(x, "x", R * C),
+                            _ptr(y, "y", (R // 2) * (C // 2)), _stream(s)))
+    return y
+
+
+def apply2_T(s, h, r, x=None):
+    """x = H^T C^T P^T r (rows x cols)."""
+    import torch
+    R, C = _shape2(s)
+    if x is None:
+        x = torch.empty(R, C, device=s.device, dtype=torch.float32)
+    _check(load().cs2_apply_T(_ptr(s, "s"), _ptr(h, "h", R * C), R, C, _ptr(r, "r", (R // 2) * (C // 2)),
+                              _ptr(x, "x", R * C), _stream(s)))
+    return x
+
+
+def norm_bound2(s, h, out=None):
+    """max |DFT2(s) DFT2(h)|^2 as a 1-element device tensor."""
+    import torch
+    R, C = _shape2(s)
+    if out is None:
+        out = torch.empty(1, device=s.device, dtype=torch.float32)
+    _check(load().cs2_norm_bound(_ptr(s, "s"), _ptr(h, "h", R * C), R, C, _ptr(out, "out", 1), _stream(s)))
+    return out
+
+
+def ista_solve2(s, h, y, lam, tau, iters, x=None, obj=None):
+    """ISTA (Alg. 1) on the 2-D operator from x(0) = 0; returns x(iters)."""
+    import torch
+    R, C = _shape2(s)
+    if x is None:
+        x = torch.empty(R, C, device=s.device, dtype=torch.float32)
+    _check(load().cs2_ista_solve(_ptr(s, "s"), _ptr(h, "h", R * C), R, C, _ptr(y, "y", (R // 2) * (C // 2)),
+                                 float(lam), float(tau), int(iters), _ptr(x, "x", R * C),
+                                 _ptr(obj, "obj", iters), _stream(s)))
+    return x
+
+
+def admm_solve2(s, h, y, lam, rho, iters, x=None, z=None, u=None, warm=False, obj=None):
+    """ADMM (Alg. 2) on the 2-D operator; returns (x, z, u)."""
+    import torch
+    R, C = _shape2(s)
+    mk = lambda: torch.empty(R, C, device=s.device, dtype=torch.float32)
+    x = mk() if x is None else x
+    z = mk() if z is None else z
+    u = mk() if u is None else u
+    _check(load().cs2_admm_solve(_ptr(s, "s"), _ptr(h, "h", R * C), R, C, _ptr(y, "y", (R // 2) * (C // 2)),
+                                 float(lam), float(rho), int(iters), int(bool(warm)), _ptr(x, "x", R * C),
+                                 _ptr(z, "z", R * C), _ptr(u, "u", R * C), _ptr(obj, "obj", iters), _stream(s)))
     return x, z, u
 
 

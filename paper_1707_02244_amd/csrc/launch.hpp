@@ -36,4 +36,13 @@ hipError_t launch_batch_ista(const BatchSig* sigs, int count, unsigned* queue, i
 template <int D2>
 int batch_blocks_per_cu();
 
+struct Col2Args;
+struct Row2Args;
+// 2-D path: column pass over R-point columns, row pass over H-point rows
+// (inst2d_col.hip / inst2d_row.hip)
+template <int R>
+hipError_t launch2_col(int op, int grid, const Col2Args& a, hipStream_t s);
+template <int H>
+hipError_t launch2_row(int mode, int grid, const Row2Args& a, hipStream_t s);
+
 }  // namespace cs

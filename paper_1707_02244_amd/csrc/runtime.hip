@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "cscirc.h"
+#include "rt_common.hpp"
 #include "launch.hpp"
 #include "solve_persistent.hpp"
 #include "batch.hpp"
@@ -29,11 +30,10 @@
 #include <numeric>
 
 namespace cs {
-namespace {
+namespace rt {
 
 thread_local std::string g_err;
 
-cs_status fail(cs_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 cs_status fail(cs_status st, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -44,12 +44,143 @@ cs_status fail(cs_status st, const char* fmt, ...) {
   return st;
 }
 
-#define CS_HIP(call)                                                                 \
-  do {                                                                               \
-    hipError_t e_ = (call);                                                          \
-    if (e_ != hipSuccess)                                                            \
-      return fail(CS_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));           \
-  } while (0)
+std::mutex g_mu;
+
+int ilog2(int64_t v) {
+  int r = 0;
+  while ((int64_t(1) << r) < v) ++r;
+  return r;
+}
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+float2 root(int64_t e, int64_t L) {
+  const double a = -2.0 * M_PI * double(e % L) / double(L);
+  return make_float2(float(std::cos(a)), float(std::sin(a)));
+}
+
+__global__ void k_fill(float* __restrict__ p, size_t count, float v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) p[i] = v;
+}
+
+cs_status fill(float* p, size_t count, float v, hipStream_t s) {
+  if (count == 0) return CS_OK;
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  k_fill<<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(p, count, v);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
+}
+
+// Objective trace: block t adds the row-pass residual partials res[t][*]
+// and the column-pass l1 partials l1[t][*] in a fixed order and writes
+//   obj[t] = 1/(2m) sum res + lambda sum l1    (Eq. 3 halved, Parseval)
+__global__ void k_objective(const double* __restrict__ res, int nres, const double* __restrict__ l1, int nl1,
+                            double inv_2m, double lambda, float* __restrict__ obj) {
+  __shared__ double r0[256], r1[256];
+  const int t = blockIdx.x;
+  const double* p0 = res + (size_t)t * nres;
+  const double* p1 = l1 + (size_t)t * nl1;
+  double a0 = 0.0, a1 = 0.0;
+  for (int i = threadIdx.x; i < nres; i += 256) a0 += p0[i];
+  for (int i = threadIdx.x; i < nl1; i += 256) a1 += p1[i];
+  r0[threadIdx.x] = a0;
+  r1[threadIdx.x] = a1;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) { r0[threadIdx.x] += r0[threadIdx.x + k]; r1[threadIdx.x] += r1[threadIdx.x + k]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) obj[t] = float(inv_2m * r0[0] + lambda * r1[0]);
+}
+
+cs_status objective_reduce(const double* res, int nres, const double* l1, int nl1, double inv_2m,
+                           double lambda, float* obj, int iters, hipStream_t s) {
+  if (iters <= 0) return CS_OK;
+  k_objective<<<dim3(iters), dim3(256), 0, s>>>(res, nres, l1, nl1, inv_2m, lambda, obj);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
+}
+
+__global__ void k_max_abs2(const float2* __restrict__ t, int count, float* __restrict__ out) {
+  __shared__ float red[256];
+  float m = 0.0f;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+    m = fmaxf(m, cabs2(t[i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + k]);
+    __syncthreads();
+  }
+  // non-negative floats order like their bit patterns
+  if (threadIdx.x == 0) atomicMax(reinterpret_cast<unsigned int*>(out), __float_as_uint(red[0]));
+}
+
+cs_status max_abs2(const float2* t, int count, float* out, hipStream_t s) {
+  int blocks = (count + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  k_max_abs2<<<dim3(blocks), dim3(256), 0, s>>>(t, count, out);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
+}
+
+// Optional per-launch timing (diagnostics): each solver kernel launch is
+// bracketed by two hipEvents on its own stream.
+struct TimedLaunch {
+  int kind;
+  hipEvent_t start, stop;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimedLaunch> g_timed;
+std::vector<TimedLaunch> g_open;
+std::vector<hipEvent_t> g_event_pool;
+const char* kTimedNames[T_COUNT] = {"passA_ista", "passB_ista", "passA_admm", "passB_admm",
+                                    "solve_ista", "solve_admm", "batch_ista",
+                                    "col2_ista", "row2_ista", "col2_admm", "row2_admm"};
+
+hipEvent_t take_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+bool timing_on() {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  return g_timing;
+}
+
+hipError_t timed_mark(int kind, hipStream_t s, long* tok) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (*tok < 0) {
+    TimedLaunch t{kind, take_event(), take_event()};
+    if (!t.start || !t.stop) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(t.start, s);
+    if (e != hipSuccess) return e;
+    *tok = long(g_open.size());
+    g_open.push_back(t);
+    return hipSuccess;
+  }
+  TimedLaunch t = g_open[size_t(*tok)];
+  g_open.erase(g_open.begin() + *tok);
+  hipError_t e = hipEventRecord(t.stop, s);
+  if (e != hipSuccess) return e;
+  g_timed.push_back(t);
+  return hipSuccess;
+}
+
+}  // namespace rt
+
+namespace {
+using namespace rt;
 
 constexpr int64_t kMinN = 256;
 constexpr int64_t kMaxN = int64_t(1) << 25;
@@ -58,13 +189,6 @@ constexpr int kMaxLogNPersistent = 21;
 
 // 0: choose per size; 1: two launches per iteration; 2: persistent launch
 int g_path = 0;
-
-int ilog2(int64_t v) {
-  int r = 0;
-  while ((int64_t(1) << r) < v) ++r;
-  return r;
-}
-bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
 struct Plan {
   int dev = 0;
@@ -86,14 +210,7 @@ struct Plan {
   }
 };
 
-std::mutex g_mu;
 std::map<std::tuple<int, int64_t, int>, std::unique_ptr<Plan>> g_plans;
-
-// exp(-2 pi i e / L) in double precision, rounded to float.
-float2 root(int64_t e, int64_t L) {
-  const double a = -2.0 * M_PI * double(e % L) / double(L);
-  return make_float2(float(std::cos(a)), float(std::sin(a)));
-}
 
 int solve_blocks_per_cu_dispatch(int logN, int alg, int d2) {
   switch (logN) {
@@ -217,48 +334,6 @@ hipError_t launchB(const Plan& P, int mode, const PassBArgs& a, hipStream_t s) {
   }
 }
 
-// Optional per-launch timing (diagnostics): each solver kernel launch is
-// bracketed by two hipEvents on its own stream.
-struct TimedLaunch {
-  int kind;
-  hipEvent_t start, stop;
-};
-std::mutex g_tmu;
-bool g_timing = false;
-std::vector<TimedLaunch> g_timed;
-std::vector<hipEvent_t> g_event_pool;
-
-hipEvent_t take_event() {
-  if (!g_event_pool.empty()) {
-    hipEvent_t e = g_event_pool.back();
-    g_event_pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-enum TimedKind { T_A_ISTA = 0, T_B_ISTA, T_A_ADMM, T_B_ADMM, T_S_ISTA, T_S_ADMM, T_BATCH, T_COUNT };
-const char* kTimedNames[T_COUNT] = {"passA_ista", "passB_ista", "passA_admm", "passB_admm",
-                                    "solve_ista", "solve_admm", "batch_ista"};
-
-template <class F>
-hipError_t timed(int kind, hipStream_t s, F&& launch) {
-  if (!g_timing) return launch();
-  std::lock_guard<std::mutex> lk(g_tmu);
-  TimedLaunch t{kind, take_event(), take_event()};
-  if (!t.start || !t.stop) return hipErrorOutOfMemory;
-  hipError_t e = hipEventRecord(t.start, s);
-  if (e != hipSuccess) return e;
-  e = launch();
-  if (e != hipSuccess) return e;
-  e = hipEventRecord(t.stop, s);
-  if (e != hipSuccess) return e;
-  g_timed.push_back(t);
-  return hipSuccess;
-}
-
 hipError_t launchUA(const Plan& P, int op, int batch, const PassAArgs& a, const UStride& st, hipStream_t s) {
   const int grid = P.N1 / 2;
   const int d2 = P.d / 2;
@@ -299,11 +374,6 @@ PassBArgs argsB(const Plan& P) {
   return b;
 }
 
-#define CS_LAUNCH(call)                                                              \
-  do {                                                                               \
-    hipError_t e_ = (call);                                                          \
-    if (e_ != hipSuccess) return fail(CS_EHIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
-  } while (0)
 
 // c_hat table from c (pass B forward on the real signal, pass A split).
 cs_status setup_chat(const Plan& P, const float* c, hipStream_t s) {
@@ -324,21 +394,6 @@ cs_status setup_yhat(const Plan& P, const float* y, hipStream_t s) {
   PassAArgs a = argsA(P);
   a.table = P.yhat;
   CS_LAUNCH(launchA(P, A_SPEC, a, s));
-  return CS_OK;
-}
-
-__global__ void k_fill(float* __restrict__ p, size_t count, float v) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (; i < count; i += stride) p[i] = v;
-}
-
-cs_status fill(float* p, size_t count, float v, hipStream_t s) {
-  if (count == 0) return CS_OK;
-  size_t blocks = (count + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  k_fill<<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(p, count, v);
-  CS_HIP(hipGetLastError());
   return CS_OK;
 }
 
@@ -394,21 +449,6 @@ int batch_blocks_dispatch(int d2) {
   }
 }
 
-__global__ void k_max_abs2(const float2* __restrict__ t, int count, float* __restrict__ out) {
-  __shared__ float red[256];
-  float m = 0.0f;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
-    m = fmaxf(m, cabs2(t[i]));
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if (threadIdx.x < k) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + k]);
-    __syncthreads();
-  }
-  // non-negative floats order like their bit patterns
-  if (threadIdx.x == 0) atomicMax(reinterpret_cast<unsigned int*>(out), __float_as_uint(red[0]));
-}
-
 cs_status check_common(const void* c, int64_t n, int d) {
   if (!c) return fail(CS_EINVAL, "c is NULL");
   if (!is_pow2(n) || n < kMinN || n > kMaxN)
@@ -445,28 +485,6 @@ __global__ void k_unrolled_grads(const double* __restrict__ part, int count, con
     g_lam[t] = float(tt * r0[0]);
     g_tau[t] = float(ll * r0[0] + r1[0] / tt);
   }
-}
-
-// Objective trace: block t adds the row-pass residual partials res[t][*]
-// and the column-pass l1 partials l1[t][*] in a fixed order and writes
-//   obj[t] = 1/(2m) sum res + lambda sum l1    (Eq. 3 halved, Parseval)
-__global__ void k_objective(const double* __restrict__ res, int nres, const double* __restrict__ l1, int nl1,
-                            double inv_2m, double lambda, float* __restrict__ obj) {
-  __shared__ double r0[256], r1[256];
-  const int t = blockIdx.x;
-  const double* p0 = res + (size_t)t * nres;
-  const double* p1 = l1 + (size_t)t * nl1;
-  double a0 = 0.0, a1 = 0.0;
-  for (int i = threadIdx.x; i < nres; i += 256) a0 += p0[i];
-  for (int i = threadIdx.x; i < nl1; i += 256) a1 += p1[i];
-  r0[threadIdx.x] = a0;
-  r1[threadIdx.x] = a1;
-  __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if (threadIdx.x < k) { r0[threadIdx.x] += r0[threadIdx.x + k]; r1[threadIdx.x] += r1[threadIdx.x + k]; }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) obj[t] = float(inv_2m * r0[0] + lambda * r1[0]);
 }
 
 // Partial-sum buffers of an objective trace over `iters` iterations:
@@ -935,10 +953,7 @@ cs_status cs_circ_norm_bound(const float* c, int64_t n, float* out, cs_stream st
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
   if ((st = fill(out, 1, 0.0f, s)) != CS_OK) return st;
-  int blocks = (P->N + 1 + 255) / 256;
-  if (blocks > 1024) blocks = 1024;
-  k_max_abs2<<<dim3(blocks), dim3(256), 0, s>>>(P->chat, P->N + 1, out);
-  CS_HIP(hipGetLastError());
+  if ((st = max_abs2(P->chat, P->N + 1, out, s)) != CS_OK) return st;
   g_err.clear();
   return CS_OK;
 }
@@ -997,8 +1012,8 @@ cs_status cs_ista_solve(const float* c, int64_t n, int32_t d, const float* y, fl
   if (obj) {
     a.res = res + size_t(iters - 1) * nres;
     CS_LAUNCH(launchA(*P, A_RES, a, s));
-    k_objective<<<dim3(iters), dim3(256), 0, s>>>(res, nres, l1, nl1, 0.5 / double(n / d), double(lambda), obj);
-    CS_HIP(hipGetLastError());
+    if ((st = objective_reduce(res, nres, l1, nl1, 0.5 / double(n / d), double(lambda), obj, iters, s)) != CS_OK)
+      return st;
   }
   g_err.clear();
   return CS_OK;
@@ -1073,8 +1088,8 @@ cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, fl
     CS_LAUNCH(timed(T_B_ADMM, s, [&] { return launchB(*P, B_ADMM, b, s); }));
   }
   if (obj) {
-    k_objective<<<dim3(iters), dim3(256), 0, s>>>(res, nres, l1, nl1, 0.5 / double(n / d), double(lambda), obj);
-    CS_HIP(hipGetLastError());
+    if ((st = objective_reduce(res, nres, l1, nl1, 0.5 / double(n / d), double(lambda), obj, iters, s)) != CS_OK)
+      return st;
   }
   g_err.clear();
   return CS_OK;

@@ -15,7 +15,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 def declared_symbols():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(cs_[a-z_A-Z0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(cs2?_[a-z_A-Z0-9]+)\s*\(", text)))
 
 
 def test_header_declares_expected_calls():
@@ -97,3 +97,21 @@ def test_package_has_no_oracle_dependency():
             if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 text = open(os.path.join(root, f)).read()
                 assert "oracle" not in text.lower(), f
+
+
+@pytest.mark.parametrize("rows,cols", [(8, 64), (64, 8), (48, 64), (64, 8192), (16384, 64)])
+def test_bad_2d_shapes_rejected(rows, cols):
+    lib = cs.load()
+    assert lib.cs2_apply(FAKE, NULL, rows, cols, FAKE, FAKE, NULL) == _lib.CS_EINVAL
+    assert lib.cs2_admm_solve(FAKE, NULL, rows, cols, FAKE, 0.1, 1.0, 5, 0, FAKE, FAKE, FAKE, NULL, NULL) == _lib.CS_EINVAL
+
+
+def test_bad_2d_arguments_rejected():
+    lib = cs.load()
+    assert lib.cs2_apply(NULL, NULL, 64, 64, FAKE, FAKE, NULL) == _lib.CS_EINVAL
+    assert lib.cs2_apply(FAKE, NULL, 64, 64, NULL, FAKE, NULL) == _lib.CS_EINVAL
+    assert lib.cs2_ista_solve(FAKE, NULL, 64, 64, FAKE, -1.0, 0.1, 5, FAKE, NULL, NULL) == _lib.CS_EINVAL
+    assert lib.cs2_ista_solve(FAKE, NULL, 64, 64, FAKE, 0.1, 0.0, 5, FAKE, NULL, NULL) == _lib.CS_EINVAL
+    assert lib.cs2_admm_solve(FAKE, NULL, 64, 64, FAKE, 0.1, 0.0, 5, 0, FAKE, FAKE, FAKE, NULL, NULL) == _lib.CS_EINVAL
+    assert lib.cs2_admm_solve(FAKE, NULL, 64, 64, FAKE, 0.1, 1.0, -2, 0, FAKE, FAKE, FAKE, NULL, NULL) == _lib.CS_EINVAL
+    assert b"rows" in lib.cs_last_error() or b"iters" in lib.cs_last_error()
