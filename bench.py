@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-2d", action="store_true")
+    ap.add_argument("--no-unrolled", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the solver path is single-GPU "
@@ -161,6 +163,10 @@ def main():
 
     if not args.no_batched:
         out["batched"] = bench_batched(cs, torch, dev, args.steps, args.warmup)
+    if not args.no_2d:
+        out["deblur_2d"] = bench_2d(cs, torch, dev, args.steps, args.warmup, not args.no_cpu_baseline)
+    if not args.no_unrolled:
+        out["unrolled"] = bench_unrolled(cs, torch, dev, args.steps, args.warmup)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sig, prm, tau, lam)
@@ -213,6 +219,118 @@ def bench_batched(cs, torch, dev, steps, warmup):
             "signal_iterations_per_s": len(sigs) * iters / (ms / 1e3),
             "model_GBs": bytes_it * iters / (ms / 1e3) / 1e9,
             "equiv_n2e22_it_s": sum_n * iters / (1 << 22) / (ms / 1e3)}
+
+
+def bench_2d(cs, torch, dev, steps, warmup, with_oracle):
+    """4096 x 4096 compressed deblurring: 20000 lognormal point sources,
+    Gaussian PSF (sigma 2, 15 x 15), +-1 sensing kernel, 2x2 decimation,
+    ADMM rho = 1, 200 iterations per solve (setup of DFT2(s) DFT2(h) and
+    DFT2(y) included in each solve).  y and lam from the library's operators."""
+    import workloads
+    sc = workloads.cfg3()
+    prm = workloads.CFG3_PARAMS
+    R, C = sc.n1, sc.n2
+    s_ = torch.from_numpy(sc.s).to(dev)
+    h_ = torch.from_numpy(sc.h).to(dev)
+    y = cs.apply2(s_, h_, torch.from_numpy(sc.x_true).to(dev))
+    lam = float(prm["lam_frac"] * cs.apply2_T(s_, h_, y).abs().max().item())
+    rho, T = prm["rho"], prm["admm_iters"]
+    x, z, u = (torch.empty(R, C, device=dev) for _ in range(3))
+    run = lambda: cs.admm_solve2(s_, h_, y, lam, rho, T, x=x, z=z, u=u)
+    for _ in range(max(1, warmup)):
+        run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    # bytes per launch: column pass reads and writes the transposed spectrum
+    # (n/2 complex), reads g_hat ((C/4 + 1) * 2R complex) and Y_hat
+    # ((C/4 + 1) * R/2 complex); row pass reads and writes the spectrum and u.
+    n = R * C
+    H = C // 2
+    col_b = 8 * n + 8 * (H // 2 + 1) * 2 * R + 8 * (H // 2 + 1) * (R // 2)
+    row_b = 8 * n + 8 * n
+    cs.timing_enable(True)
+    run()
+    torch.cuda.synchronize()
+    cs.timing_enable(False)
+    kern = {}
+    for name, b in (("col2_admm", col_b), ("row2_admm", row_b)):
+        cnt, tot = cs.timing_read(name)
+        if cnt:
+            kern[name] = {"launches": cnt, "avg_us": 1e3 * tot / cnt, "bytes_per_launch": b,
+                          "GBs": b / (tot / cnt / 1e3) / 1e9}
+    it_bytes = col_b + row_b
+    out = {"workload": "4096x4096 deblurring: 20000 lognormal sources, Gaussian PSF sigma=2 (15x15), "
+                       "+-1 sensing kernel, 2x2 decimation; ADMM rho=1, 200 it per solve",
+           "ms_per_solve": ms, "iterations_per_s": T / (ms / 1e3),
+           "bytes_per_iteration": it_bytes, "model_GBs": it_bytes * T / (ms / 1e3) / 1e9,
+           "kernels": kern}
+    if kern:
+        dom = max(kern, key=lambda k: kern[k]["avg_us"])
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": kern[dom]["GBs"], "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": kern[dom]["GBs"] / HBM_PEAK_GBS, "traffic": None}
+    if with_oracle:
+        from oracle import twod
+        pr_lam = lam
+        op = twod.Operator2D(sc.s.astype(np.float64), sc.h.astype(np.float64), 2, 2)
+        yy = y.cpu().numpy().astype(np.float64).ravel()
+        k = 2
+        t0 = time.perf_counter()
+        twod.admm(op, yy, pr_lam, rho, k)
+        dt = (time.perf_counter() - t0) / k
+        out["oracle"] = {"iterations_per_s": 1.0 / dt, "cores": len(os.sched_getaffinity(0)),
+                         "sample": "FP64 2-D FFT reference (scipy.fft, all cores): %d ADMM iterations at "
+                                   "4096x4096" % k}
+    return out
+
+
+def bench_unrolled(cs, torch, dev, steps, warmup):
+    """Unrolled ISTA, K = 50 steps, 64 signals of n = 2^16 sharing c (d = 4,
+    k = 256), checkpoints every 10: forward (x_K and checkpoints) and
+    backward (gradients of lam_t, tau_t and y from dL/dx_K)."""
+    import workloads
+    prm = workloads.CFG5_PARAMS
+    c_np, xs_np = workloads.cfg5()
+    K, every, d = prm["K"], prm["every"], 4
+    n = c_np.shape[0]
+    B = xs_np.shape[0]
+    c = torch.from_numpy(c_np).to(dev)
+    xs = torch.from_numpy(xs_np).to(dev)
+    Y = torch.stack([cs.circ_apply(c, d, xs[b]) for b in range(B)])
+    lam0 = prm["lam_frac"] * max(cs.circ_apply_T(c, d, Y[b]).abs().max().item() for b in range(B))
+    tau0 = 1.0 / cs.circ_norm_bound(c).item()
+    lam = torch.full((K,), lam0, device=dev)
+    tau = torch.full((K,), tau0, device=dev)
+    xK, ckpt = cs.unrolled_ista_fwd(c, d, Y, lam, tau, K, every)
+    gx = 2.0 * (xK - xs)
+    for _ in range(max(1, warmup)):
+        cs.unrolled_ista_fwd(c, d, Y, lam, tau, K, every, xK=xK, ckpt=ckpt)
+        cs.unrolled_ista_bwd(c, d, Y, lam, tau, K, every, ckpt, gx)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd = bwd = 0.0
+    for _ in range(steps):
+        ev[0].record()
+        cs.unrolled_ista_fwd(c, d, Y, lam, tau, K, every, xK=xK, ckpt=ckpt)
+        ev[1].record()
+        cs.unrolled_ista_bwd(c, d, Y, lam, tau, K, every, ckpt, gx)
+        ev[2].record()
+        torch.cuda.synchronize()
+        fwd += ev[0].elapsed_time(ev[1])
+        bwd += ev[1].elapsed_time(ev[2])
+    fwd /= steps
+    bwd /= steps
+    m = n // d
+    it_bytes = B * (28 * n + 4 * m)   # per step, all signals: row pass 12n + 4m, column pass 16n
+    return {"workload": "unrolled ISTA K=50, 64 signals n=2^16 sharing c (d=4, k=256), checkpoints every 10",
+            "fwd_ms": fwd, "bwd_ms": bwd, "bwd_over_fwd": bwd / fwd,
+            "fwd_steps_per_s": K / (fwd / 1e3), "fwd_signal_steps_per_s": B * K / (fwd / 1e3),
+            "fwd_model_GBs": it_bytes * K / (fwd / 1e3) / 1e9}
 
 
 def cpu_baseline(sig, prm, tau, lam):
