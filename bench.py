@@ -64,6 +64,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-2d", action="store_true")
     ap.add_argument("--no-unrolled", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain copy kernel (read and write this many MiB, 3 launches): the "
+                         "known-size reference that scales profiler byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the solver path is single-GPU "
@@ -167,6 +170,15 @@ def main():
         out["deblur_2d"] = bench_2d(cs, torch, dev, args.steps, args.warmup, not args.no_cpu_baseline)
     if not args.no_unrolled:
         out["unrolled"] = bench_unrolled(cs, torch, dev, args.steps, args.warmup)
+
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"kernel": "torch.neg (elementwise)", "bytes_read": 4 * src.numel(),
+                                   "bytes_written": 4 * dst.numel(), "launches": 3}
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sig, prm, tau, lam)
