@@ -14,9 +14,8 @@
 //                columns; consecutive threads take consecutive b so every
 //                LDS access of a stage is unit-stride across the wave)
 // Each stage loads its butterflies into registers, barriers, then stores in
-// place, so LDS holds one copy of the data.  LDS addresses are padded by one
-// slot per 16 (flat index x lives at x + x/16): with that skew the strided
-// stores of the early radix-16 stages hit distinct banks.  Twiddles come from a table
+// place, so LDS holds one copy of the data.  Every LDS address goes through
+// the bank swizzle lp() below.  Twiddles come from a table
 // tw[e] = exp(-2 pi i e / L), e < L, computed on the host in double precision.
 // Forward transforms use exp(-...), inverse ones exp(+...), both unnormalised.
 #pragma once
@@ -44,14 +43,24 @@ constexpr int stage_radix(int L, int NS) {
   return (p % 3 == 0) ? 8 : ((p % 3 == 2) ? 4 : (p == 1 ? 2 : 4));
 }
 
-#ifndef CS_LDS_PAD
-#define CS_LDS_PAD 0
+#ifndef CS_LDS_SWIZZLE
+#define CS_LDS_SWIZZLE 0
 #endif
-// LDS slot of flat index x: with CS_LDS_PAD, one padding slot per 16 (skews
-// the strided stores of early stages across banks, at the price of address
-// arithmetic the compiler cannot fold into instruction offsets)
-__device__ __forceinline__ unsigned lp(unsigned x) { return CS_LDS_PAD ? x + (x >> 4) : x; }
-constexpr int lds_padded(int n) { return CS_LDS_PAD ? n + n / 16 + 1 : n; }
+// LDS slot of flat index x.  With CS_LDS_SWIZZLE every slot keeps its
+// aligned block of 32 float2 (the 64 four-byte banks) and is XORed within it
+// by a function of the block index g = (x >> 5) mod 32:
+// slot x ^ (g ^ (g >> 4) ^ (g << 2)) mod 32.  Unit-stride accesses stay
+// conflict-free (a permutation inside a block) while the strided stores of
+// the early Stockham stages spread over all banks, at the price of the
+// address arithmetic.  Buffers are then whole blocks (lds_padded).
+__device__ __forceinline__ unsigned lp(unsigned x) {
+  if (CS_LDS_SWIZZLE) {
+    const unsigned g = (x >> 5) & 31u;
+    return x ^ ((g ^ (g >> 4) ^ (g << 2)) & 31u);
+  }
+  return x;
+}
+constexpr int lds_padded(int n) { return CS_LDS_SWIZZLE ? ((n + 31) & ~31) : n; }
 
 // multiply by the primitive 8th root of unity W8^q (q = 1, 3), forward sign
 // exp(-i pi q / 4) or inverse sign exp(+i pi q / 4).

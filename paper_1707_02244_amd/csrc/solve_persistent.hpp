@@ -17,6 +17,13 @@
 // L2-resident c_hat / y_hat reads.  All twiddle tables (FFT stages, four-step,
 // real split) are loaded into LDS once per launch.
 //
+// Y interleaves each mirror row pair: element (k1, j2) of the four-step
+// intermediate lives at Y[(w * N2 + j2) * 2 + s], where pair w holds rows w
+// (s = 0) and N1 - w (s = 1), and pair 0 holds rows 0 and N1/2.  A row-pass
+// workgroup then reads and writes one contiguous block of 2 N2 values per
+// pair, and a column-pass workgroup (8 adjacent columns) moves 128-byte runs
+// (8 columns x 2 rows) instead of 64-byte ones.
+//
 // Grid size G = N2 / CB; the split is chosen so that N1/2 = AI * G with AI = 1
 // or 2.  The launch is cooperative (hipLaunchCooperativeKernel), so all G
 // workgroups are resident and the barrier's wait always ends; the wait is also
@@ -165,6 +172,18 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
   // 32-bit offset lets the compiler use scalar-base addressing
   static_assert(T % CB == 0, "");
   auto col_index = [&](unsigned e) -> unsigned { return (e / CB) * N2 + j2_0 + (e % CB); };
+  // column-pass access to Y: slot e of the workgroup's block in Y order
+  // (pair w = e / (2 CB), column c = (e / 2) % CB, side s = e % 2) -> its
+  // Y offset and its LDS element (row k1, column c) in the interleaved
+  // column layout k1 * CB + c
+  auto ycol_off = [&](unsigned e) -> unsigned {
+    return (e / (2 * CB)) * (2 * N2) + (j2_0 + (e / 2) % CB) * 2 + (e & 1);
+  };
+  auto ycol_lds = [&](unsigned e) -> unsigned {
+    const unsigned w = e / (2 * CB), c = (e / 2) % CB;
+    const unsigned k1 = (e & 1) ? (w ? N1 - w : (N1 >> 1)) : w;
+    return k1 * CB + c;
+  };
 
   // forward column transform of lds (time domain) and store to Y
   auto col_forward_store = [&]() {
@@ -172,7 +191,10 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
 #pragma unroll
     for (int k = 0; k < EB; ++k) {
       const unsigned e = tid + k * T;
-      if (FB || e < NEB) st_coh(&Yg[col_index(e)], cmul(lds[lp(e)], twb(e)));
+      if (FB || e < NEB) {
+        const unsigned li = ycol_lds(e);
+        st_coh(&Yg[ycol_off(e)], cmul(lds[lp(li)], twb(li)));
+      }
     }
   };
 
@@ -209,10 +231,9 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
       for (int k = 0; k < EA; ++k) {
         const unsigned i = tid + k * T;
         if (FA || i < RA * N2) {
-          const unsigned s = i / N2, p = i % N2;
-          const unsigned w = g + (s >> 1) * G;
-          const unsigned row = (s & 1) ? (w ? N1 - w : (N1 >> 1)) : w;
-          rv[k] = zero_in ? c2(0.f, 0.f) : ld_coh(&Yg[(unsigned)row * N2 + p]);
+          // pair i / (2 N2) of this workgroup, one contiguous block
+          const unsigned w = g + (i / (2 * N2)) * G;
+          rv[k] = zero_in ? c2(0.f, 0.f) : ld_coh(&Yg[w * (2 * N2) + i % (2 * N2)]);
         }
       }
 #pragma unroll
@@ -233,7 +254,8 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
 #pragma unroll
       for (int k = 0; k < EA; ++k) {
         const unsigned i = tid + k * T;
-        if (FA || i < RA * N2) lds[lp((i / N2) * LDA + (i % N2))] = rv[k];
+        // slot 2 * pair + side, position j2
+        if (FA || i < RA * N2) lds[lp((2 * (i / (2 * N2)) + (i & 1)) * LDA + (i % (2 * N2)) / 2)] = rv[k];
       }
     }
     __syncthreads();
@@ -311,10 +333,9 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
     for (int k = 0; k < EA; ++k) {
       const unsigned i = tid + k * T;
       if (FA || i < RA * N2) {
-        const unsigned s = i / N2, p = i % N2;
-        const unsigned w = g + (s >> 1) * G;
-        const unsigned row = (s & 1) ? (w ? N1 - w : (N1 >> 1)) : w;
-        st_coh(&Yg[(unsigned)row * N2 + p], lds[lp(s * LDA + p)]);
+        const unsigned w = g + (i / (2 * N2)) * G;
+        st_coh(&Yg[w * (2 * N2) + i % (2 * N2)],
+               lds[lp((2 * (i / (2 * N2)) + (i & 1)) * LDA + (i % (2 * N2)) / 2)]);
       }
     }
     grid_barrier(a.bar, (++nbar) * G, a.err);
@@ -325,12 +346,15 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
 #pragma unroll
       for (int k = 0; k < EB; ++k) {
         const unsigned e = tid + k * T;
-        if (FB || e < NEB) cv[k] = ld_coh(&Yg[col_index(e)]);
+        if (FB || e < NEB) cv[k] = ld_coh(&Yg[ycol_off(e)]);
       }
 #pragma unroll
       for (int k = 0; k < EB; ++k) {
-          const unsigned e = tid + k * T;
-        if (FB || e < NEB) lds[lp(e)] = cmulc(cv[k], twb(e));
+        const unsigned e = tid + k * T;
+        if (FB || e < NEB) {
+          const unsigned li = ycol_lds(e);
+          lds[lp(li)] = cmulc(cv[k], twb(li));
+        }
       }
     }
     __syncthreads();
