@@ -46,6 +46,9 @@ constexpr int stage_radix(int L, int NS) {
 #ifndef CS_LDS_SWIZZLE
 #define CS_LDS_SWIZZLE 0
 #endif
+#ifndef CS_LDS_PAD32
+#define CS_LDS_PAD32 0
+#endif
 // LDS slot of flat index x.  With CS_LDS_SWIZZLE every slot keeps its
 // aligned block of 32 float2 (the 64 four-byte banks) and is XORed within it
 // by a function of the block index g = (x >> 5) mod 32:
@@ -58,9 +61,12 @@ __device__ __forceinline__ unsigned lp(unsigned x) {
     const unsigned g = (x >> 5) & 31u;
     return x ^ ((g ^ (g >> 4) ^ (g << 2)) & 31u);
   }
+  if (CS_LDS_PAD32) return x + (x >> 5);   // one pad slot after every 32
   return x;
 }
-constexpr int lds_padded(int n) { return CS_LDS_SWIZZLE ? ((n + 31) & ~31) : n; }
+constexpr int lds_padded(int n) {
+  return CS_LDS_SWIZZLE ? ((n + 31) & ~31) : (CS_LDS_PAD32 ? n + n / 32 + 1 : n);
+}
 
 // multiply by the primitive 8th root of unity W8^q (q = 1, 3), forward sign
 // exp(-i pi q / 4) or inverse sign exp(+i pi q / 4).

@@ -9,9 +9,11 @@
 //   X[k1][k2] = E + w O,   X[k1][k2 + H] = E - w O.
 //
 // Row pass ("time side"): a workgroup owns kRows2 = 8 image rows and runs
-// H-point FFTs along them.  The row-transformed image is stored transposed,
-// T[k2][r], so the row pass moves 64-byte runs (8 rows) and the column pass
-// whole contiguous columns.  The time-domain steps (soft threshold, Eq. 4;
+// H-point FFTs along them.  The row-transformed image is stored transposed
+// with each mirror column pair interleaved: T[w][r][s] holds column k2 = w
+// (s = 0) and its mirror H - w (s = 1; pair 0 holds columns 0 and H/2).  The
+// column pass then reads one contiguous block per workgroup and the row pass
+// 128-byte runs (8 rows x the two columns of a pair).  The time-domain steps (soft threshold, Eq. 4;
 // ADMM's z and u updates, Alg. 2) run between the inverse and the forward
 // row transforms.
 //
@@ -38,7 +40,19 @@
 
 namespace cs {
 
-constexpr int kRows2 = 8;     // image rows per row-pass workgroup (64-byte runs of T)
+#ifndef CS_ROWS2
+#define CS_ROWS2 8
+#endif
+#ifndef CS_COL2_MINW
+#define CS_COL2_MINW 1   // column pass: minimum waves per SIMD the compiler must allow
+#endif
+#ifndef CS_ROW2_MINW
+#define CS_ROW2_MINW 1   // row pass: same
+#endif
+#ifndef CS_ROW2_TWLDS
+#define CS_ROW2_TWLDS 1  // row pass: FFT twiddles staged in LDS (else read from the global table)
+#endif
+constexpr int kRows2 = CS_ROWS2;   // image rows per row-pass workgroup (8: 64-byte runs of T)
 constexpr int kPad2 = CS_LDS_SWIZZLE ? 0 : 4;   // float2 padding between LDS rows / columns
 
 enum OpC2 : int {
@@ -63,7 +77,7 @@ enum ModeR2 : int {
 };
 
 struct Col2Args {
-  float2* T;               // [H][R]: T[k2][r]
+  float2* T;               // [H/2][R][2]: column pairs {w, H - w} ({0, H/2} for w = 0)
   const float2* G;         // g_hat: [H/2 + 1][2][R], G[p][l2][k1] = g_hat(k1, p + l2 H)
   const float2* Yt;        // Y_hat: [H/2 + 1][R/2], Yt[p][k1'] = Y_hat(k1', p)
   float2* table;           // C2_SPEC / C2_SPECMUL (G layout), C2_YHAT (Yt layout)
@@ -77,7 +91,7 @@ struct Col2Args {
 };
 
 struct Row2Args {
-  float2* T;               // [H][R]
+  float2* T;               // [H/2][R][2], as in Col2Args
   const float2* twH;       // W_H^e, e < H
   int R;
   int H;
@@ -91,15 +105,21 @@ struct Row2Args {
   double* l1;              // objective trace: per-workgroup sum |x|
 };
 
+#ifndef CS_COL2_T
+#define CS_COL2_T 512    // column-pass threads for R >= 2048
+#endif
+#ifndef CS_ROW2_T
+#define CS_ROW2_T 512    // row-pass threads for 8 H >= 8192
+#endif
 template <int R>
-constexpr int col2_threads() { return R >= 2048 ? 512 : 256; }
+constexpr int col2_threads() { return R >= 2048 ? CS_COL2_T : 256; }
 template <int H>
-constexpr int row2_threads() { return kRows2 * H >= 8192 ? 512 : 256; }
+constexpr int row2_threads() { return kRows2 * H >= 8192 ? CS_ROW2_T : 256; }
 
 // ---------------------------------------------------------------------------
 // Column pass (frequency side).
 template <int R, int OP>
-__global__ __launch_bounds__(col2_threads<R>()) void k2_col(Col2Args a) {
+__global__ __launch_bounds__(col2_threads<R>(), CS_COL2_MINW) void k2_col(Col2Args a) {
   constexpr int T = col2_threads<R>();
   constexpr int LD = R + kPad2;
   constexpr int NE = 2 * R;
@@ -121,7 +141,7 @@ __global__ __launch_bounds__(col2_threads<R>()) void k2_col(Col2Args a) {
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const unsigned i = tid + k * T;
-    if (NE % T == 0 || i < NE) v[k] = a.T[(size_t)((i / R) ? col1 : col0) * R + (i % R)];
+    if (NE % T == 0 || i < NE) v[k] = a.T[(size_t)w * NE + i];   // element (r = i/2, slot i%2)
   }
   // group operands: g_hat at the class's four bins, Y_hat of the class
   constexpr int NGMAX = HR;   // groups per workgroup (w > 0); workgroup 0 has R/2 + 2
@@ -151,7 +171,7 @@ __global__ __launch_bounds__(col2_threads<R>()) void k2_col(Col2Args a) {
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const unsigned i = tid + k * T;
-    if (NE % T == 0 || i < NE) lds[lp((i / R) * LD + (i % R))] = v[k];
+    if (NE % T == 0 || i < NE) lds[lp((i & 1) * LD + (i >> 1))] = v[k];
   }
   __syncthreads();
   lds_fft<R, 2, T, false, false, LD>(lds, tws, tid);
@@ -262,7 +282,7 @@ __global__ __launch_bounds__(col2_threads<R>()) void k2_col(Col2Args a) {
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       const unsigned i = tid + k * T;
-      if (NE % T == 0 || i < NE) a.T[(size_t)((i / R) ? col1 : col0) * R + (i % R)] = lds[lp((i / R) * LD + (i % R))];
+      if (NE % T == 0 || i < NE) a.T[(size_t)w * NE + i] = lds[lp((i & 1) * LD + (i >> 1))];
     }
   }
 }
@@ -270,7 +290,7 @@ __global__ __launch_bounds__(col2_threads<R>()) void k2_col(Col2Args a) {
 // ---------------------------------------------------------------------------
 // Row pass (time side): workgroup b owns image rows [8b, 8b + 8).
 template <int H, int MODE>
-__global__ __launch_bounds__(row2_threads<H>()) void k2_row(Row2Args a) {
+__global__ __launch_bounds__(row2_threads<H>(), CS_ROW2_MINW) void k2_row(Row2Args a) {
   constexpr int T = row2_threads<H>();
   constexpr int RW = kRows2;
   constexpr int LD = H + kPad2;
@@ -280,27 +300,39 @@ __global__ __launch_bounds__(row2_threads<H>()) void k2_row(Row2Args a) {
   constexpr bool FULL = (NE % T) == 0;
   constexpr bool HAS_INV = (MODE == R2_ISTA || MODE == R2_ADMM || MODE == R2_OUT_ALL || MODE == R2_OUT_DEC);
   __shared__ float2 lds[lds_padded(RW * LD)];
-  __shared__ float2 tws[H];
+  __shared__ float2 tws_l[CS_ROW2_TWLDS ? H : 1];
+  const float2* tws = CS_ROW2_TWLDS ? tws_l : a.twH;
   const unsigned tid = threadIdx.x;
   const int r0 = blockIdx.x * RW;
   const int R = a.R;
   const size_t tbase = (size_t)r0 * H;   // first packed element of the rows (time side)
-  for (unsigned i = tid; i < H; i += T) tws[i] = a.twH[i];
+  // spectral side, element i of the block in T order: pair w = i / (2 RW),
+  // row c = (i / 2) % RW, side s = i % 2 (column w, or its mirror)
+  auto t_off = [&](unsigned i) -> size_t {
+    return ((size_t)(i / (2 * RW)) * R + r0 + (i / 2) % RW) * 2 + (i & 1);
+  };
+  auto t_lds = [&](unsigned i) -> unsigned {
+    const unsigned w = i / (2 * RW), c = (i / 2) % RW;
+    const unsigned k2 = (i & 1) ? (w ? H - w : (H >> 1)) : w;
+    return c * LD + k2;
+  };
+  if (CS_ROW2_TWLDS)
+    for (unsigned i = tid; i < H; i += T) tws_l[i] = a.twH[i];
 
   if constexpr (HAS_INV) {
-    // T[k2][r0 + c] -> lds[c][k2]: 64-byte runs of 8 rows
+    // T[w][r0 + c][s] -> lds[c][k2]: 128-byte runs (8 rows x 2 columns)
 #pragma unroll
     for (int k0 = 0; k0 < EPT; k0 += CH) {
       float2 v[CH];
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const unsigned i = tid + (k0 + k) * T;
-        if (FULL || i < NE) v[k] = a.T[(size_t)(i / RW) * R + r0 + (i % RW)];
+        if (FULL || i < NE) v[k] = a.T[t_off(i)];
       }
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const unsigned i = tid + (k0 + k) * T;
-        if (FULL || i < NE) lds[lp((i % RW) * LD + (i / RW))] = v[k];
+        if (FULL || i < NE) lds[lp(t_lds(i))] = v[k];
       }
     }
     __syncthreads();
@@ -395,7 +427,7 @@ __global__ __launch_bounds__(row2_threads<H>()) void k2_row(Row2Args a) {
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const unsigned i = tid + k * T;
-    if (FULL || i < NE) a.T[(size_t)(i / RW) * R + r0 + (i % RW)] = lds[lp((i % RW) * LD + (i / RW))];
+    if (FULL || i < NE) a.T[t_off(i)] = lds[lp(t_lds(i))];
   }
 }
 
