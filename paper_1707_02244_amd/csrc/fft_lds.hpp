@@ -15,8 +15,9 @@
 //                LDS access of a stage is unit-stride across the wave)
 // Each stage loads its butterflies into registers, barriers, then stores in
 // place, so LDS holds one copy of the data.  Every LDS address goes through
-// the bank swizzle lp() below.  Twiddles come from a table
-// tw[e] = exp(-2 pi i e / L), e < L, computed on the host in double precision.
+// lp() below.  Twiddles come from a table tw[e] = exp(-2 pi i e / L), e < L,
+// computed on the host in double precision; a butterfly reads at most three
+// of them and forms its other powers by complex products.
 // Forward transforms use exp(-...), inverse ones exp(+...), both unnormalised.
 #pragma once
 #include "cplx.hpp"
@@ -199,11 +200,30 @@ __device__ __forceinline__ void stockham_stage(float2* __restrict__ buf,
       const unsigned j = ILV ? (i / B) : (i % Q);
       const unsigned k = j & (NS - 1);
       if constexpr (NS > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const float2 w = tw[(r * k) * (L / (NS * R))];
-          v[p][r] = INV ? cmulc(v[p][r], w) : cmul(v[p][r], w);
+        // twiddles W_{NS R}^{r k}: read W^k (and W^{4k}, W^{8k} for the
+        // larger radices) from the table and form the other powers by
+        // products (chains of at most three), so a butterfly makes at most
+        // three LDS gathers instead of R - 1
+        constexpr unsigned S = L / (NS * R);
+        float2 w[R];
+        w[1] = tw[k * S];
+        if constexpr (R >= 4) {
+          w[2] = cmul(w[1], w[1]);
+          w[3] = cmul(w[2], w[1]);
         }
+        if constexpr (R >= 8) {
+          w[4] = tw[4 * k * S];
+          w[5] = cmul(w[4], w[1]);
+          w[6] = cmul(w[4], w[2]);
+          w[7] = cmul(w[4], w[3]);
+        }
+        if constexpr (R >= 16) {
+          w[8] = tw[8 * k * S];
+#pragma unroll
+          for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+        }
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[p][r] = INV ? cmulc(v[p][r], w[r]) : cmul(v[p][r], w[r]);
       }
       dft<R, INV>(v[p]);
       const unsigned base = (j - k) * R + k;
