@@ -44,30 +44,12 @@ constexpr int stage_radix(int L, int NS) {
   return (p % 3 == 0) ? 8 : ((p % 3 == 2) ? 4 : (p == 1 ? 2 : 4));
 }
 
-#ifndef CS_LDS_SWIZZLE
-#define CS_LDS_SWIZZLE 0
-#endif
-#ifndef CS_LDS_PAD32
-#define CS_LDS_PAD32 0
-#endif
-// LDS slot of flat index x.  With CS_LDS_SWIZZLE every slot keeps its
-// aligned block of 32 float2 (the 64 four-byte banks) and is XORed within it
-// by a function of the block index g = (x >> 5) mod 32:
-// slot x ^ (g ^ (g >> 4) ^ (g << 2)) mod 32.  Unit-stride accesses stay
-// conflict-free (a permutation inside a block) while the strided stores of
-// the early Stockham stages spread over all banks, at the price of the
-// address arithmetic.  Buffers are then whole blocks (lds_padded).
-__device__ __forceinline__ unsigned lp(unsigned x) {
-  if (CS_LDS_SWIZZLE) {
-    const unsigned g = (x >> 5) & 31u;
-    return x ^ ((g ^ (g >> 4) ^ (g << 2)) & 31u);
-  }
-  if (CS_LDS_PAD32) return x + (x >> 5);   // one pad slot after every 32
-  return x;
-}
-constexpr int lds_padded(int n) {
-  return CS_LDS_SWIZZLE ? ((n + 31) & ~31) : (CS_LDS_PAD32 ? n + n / 32 + 1 : n);
-}
+// LDS slot of flat index x (identity).  Bank swizzles and per-32 padding
+// were measured slower on gfx950: they stop the compiler from folding
+// constant offsets into ds_read2 / ds_write2 pairs, and the extra LDS
+// instructions cost more than the bank conflicts they remove.
+__device__ __forceinline__ unsigned lp(unsigned x) { return x; }
+constexpr int lds_padded(int n) { return n; }
 
 // multiply by the primitive 8th root of unity W8^q (q = 1, 3), forward sign
 // exp(-i pi q / 4) or inverse sign exp(+i pi q / 4).

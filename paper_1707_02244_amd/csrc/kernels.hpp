@@ -48,7 +48,7 @@ namespace cs {
 
 constexpr int kThreads = 256;
 constexpr int kColsPerBlock = 8;   // pass B: adjacent columns per workgroup (64 B runs)
-constexpr int kPadA = CS_LDS_SWIZZLE ? 0 : 4;   // pass A: float2 padding between rows
+constexpr int kPadA = 4;   // pass A: float2 padding between rows
 
 enum OpA : int {
   A_ISTA = 0,   // ISTA frequency update (alias classes)

@@ -53,7 +53,7 @@ namespace cs {
 #define CS_ROW2_TWLDS 1  // row pass: FFT twiddles staged in LDS (else read from the global table)
 #endif
 constexpr int kRows2 = CS_ROWS2;   // image rows per row-pass workgroup (8: 64-byte runs of T)
-constexpr int kPad2 = CS_LDS_SWIZZLE ? 0 : 4;   // float2 padding between LDS rows / columns
+constexpr int kPad2 = 4;   // float2 padding between LDS rows / columns
 
 enum OpC2 : int {
   C2_ISTA = 0,     // ISTA class update (step spectrum)
