@@ -197,7 +197,7 @@ struct Plan {
   int N = 0, N1 = 0, N2 = 0, M = 0, lo_bits = 0, logN = 0;
   bool persistent[2][5] = {};   // [alg][d/2 index]: cooperative launch fits
   float2* mem = nullptr;
-  unsigned* bar = nullptr;      // [0] grid barrier counter, [1] error flag
+  unsigned* bar = nullptr;      // grid barrier counters, error flag at [kBarErr]
   float2 *Y = nullptr, *chat = nullptr, *yhat = nullptr;
   float2 *tw1 = nullptr, *tw2 = nullptr, *twlo = nullptr, *twhi = nullptr;
   float2 *twk1 = nullptr, *twp = nullptr;
@@ -261,7 +261,8 @@ cs_status get_plan(int64_t n, int d, Plan** out) {
   const int64_t oY = 0, oC = oY + up(p->N), oYh = oC + up(p->N + 1), oT1 = oYh + up(p->N + 1);
   const int64_t oT2 = oT1 + up(p->N1), oLo = oT2 + up(p->N2), oHi = oLo + up(nlo);
   const int64_t oK1 = oHi + up(nhi), oP = oK1 + up(p->N1), oS = oP + up(p->N2);
-  const int64_t total = oS + 64;
+  const int64_t oB = oS + 64;   // barrier area: kBarWords unsigned
+  const int64_t total = oB + up(kBarWords / 2);
   hipError_t e = hipMalloc(&p->mem, size_t(total) * sizeof(float2));
   if (e != hipSuccess) return fail(CS_ENOMEM, "hipMalloc of %lld bytes for plan n=%lld d=%d failed: %s",
                                    (long long)(total * sizeof(float2)), (long long)n, d, hipGetErrorString(e));
@@ -269,8 +270,8 @@ cs_status get_plan(int64_t n, int d, Plan** out) {
   p->Y = b + oY; p->chat = b + oC; p->yhat = b + oYh;
   p->tw1 = b + oT1; p->tw2 = b + oT2; p->twlo = b + oLo; p->twhi = b + oHi;
   p->twk1 = b + oK1; p->twp = b + oP; p->scal = reinterpret_cast<float*>(b + oS);
-  p->bar = reinterpret_cast<unsigned*>(b + oS) + 16;
-  e = hipMemset(p->bar, 0, 2 * sizeof(unsigned));
+  p->bar = reinterpret_cast<unsigned*>(b + oB);
+  e = hipMemset(p->bar, 0, kBarWords * sizeof(unsigned));
   if (e != hipSuccess) return fail(CS_EHIP, "hipMemset of plan flags failed: %s", hipGetErrorString(e));
   if (pN >= kMinLogNPersistent && pN <= kMaxLogNPersistent) {
     int cus = 0;
@@ -411,7 +412,7 @@ SolveArgs solve_args(const Plan& P) {
   a.Y = P.Y; a.chat = P.chat; a.yhat = P.yhat;
   a.tw1 = P.tw1; a.tw2 = P.tw2; a.twlo = P.twlo; a.twhi = P.twhi; a.twk1 = P.twk1; a.twp = P.twp;
   a.lo_bits = P.lo_bits;
-  a.bar = P.bar; a.err = reinterpret_cast<int*>(P.bar + 1);
+  a.bar = P.bar; a.err = reinterpret_cast<int*>(P.bar + kBarErr);
   a.inv_n = float(1.0 / double(P.n));
   a.inv_d = float(1.0 / double(P.d));
   return a;
@@ -854,10 +855,10 @@ cs_status cs_check_device(cs_stream stream) {
     Plan& P = *kv.second;
     if (P.dev != dev) continue;
     unsigned flag = 0;
-    CS_HIP(hipMemcpy(&flag, P.bar + 1, sizeof flag, hipMemcpyDeviceToHost));
+    CS_HIP(hipMemcpy(&flag, P.bar + kBarErr, sizeof flag, hipMemcpyDeviceToHost));
     if (flag) {
       const unsigned zero = 0;
-      CS_HIP(hipMemcpy(P.bar + 1, &zero, sizeof zero, hipMemcpyHostToDevice));
+      CS_HIP(hipMemcpy(P.bar + kBarErr, &zero, sizeof zero, hipMemcpyHostToDevice));
       return fail(CS_EHIP, "a grid barrier wait exceeded its bound (n=%lld d=%d)", (long long)P.n, P.d);
     }
   }
@@ -979,8 +980,9 @@ cs_status cs_ista_solve(const float* c, int64_t n, int32_t d, const float* y, fl
   bool pers = false;
   if (!obj && (st = use_persistent(*P, 0, &pers)) != CS_OK) return st;
   if (pers) {
-    // counter and error flag start at zero (bit pattern of 0.0f)
-    if ((st = fill(reinterpret_cast<float*>(P->bar), 1, 0.0f, s)) != CS_OK) return st;
+    // barrier counters start at zero (bit pattern of 0.0f); the error flag is
+    // cleared by cs_check_device
+    if ((st = fill(reinterpret_cast<float*>(P->bar), kBarErr, 0.0f, s)) != CS_OK) return st;
     SolveArgs sa = solve_args(*P);
     sa.x = x;
     sa.iters = iters;
@@ -1045,7 +1047,7 @@ cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, fl
   bool pers = false;
   if (!obj && (st = use_persistent(*P, 1, &pers)) != CS_OK) return st;
   if (pers) {
-    if ((st = fill(reinterpret_cast<float*>(P->bar), 1, 0.0f, s)) != CS_OK) return st;
+    if ((st = fill(reinterpret_cast<float*>(P->bar), kBarErr, 0.0f, s)) != CS_OK) return st;
     SolveArgs sa = solve_args(*P);
     sa.x = x; sa.z = z; sa.u = u;
     sa.iters = iters;

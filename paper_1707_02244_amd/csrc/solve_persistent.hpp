@@ -53,7 +53,7 @@ struct SolveArgs {
   float* x;                // ISTA: output x(T).  ADMM: output x(T)
   float* z;                // ADMM: in (warm) / out z(T)
   float* u;                // ADMM: in (warm) / out u(T)
-  unsigned* bar;           // grid barrier counter, zero at launch
+  unsigned* bar;           // grid barrier counters (kBarWords words), zero at launch
   int* err;                // set to 1 if a barrier wait hit its bound
   int iters;
   int warm;
@@ -79,21 +79,38 @@ __device__ __forceinline__ void st_coh(float2* p, float2 v) {
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid-wide barrier: each wave waits until its own coherent stores have
-// completed, the workgroup synchronises, one thread arrives on the counter
-// and polls it, and a workgroup barrier releases the waves.  The wait is
-// bounded; hitting the bound sets the error flag, and a set flag ends every
+// Grid-wide barrier.  Arrivals are spread over NC counters, each on its own
+// 128-byte line (workgroup g adds to counter g mod NC): a single counter
+// serialises all G atomic adds on one line, several microseconds per barrier
+// at G = 256.  Each wave first waits until its own coherent stores have
+// completed, the workgroup synchronises, lane 0 of wave 0 arrives, and wave 0
+// polls all counters at once (lane c reads counter c) until every one has
+// reached its target; a workgroup barrier releases the other waves.  The wait
+// is bounded; hitting the bound sets the error flag, and a set flag ends every
 // later wait at once.
+constexpr int kBarCounters = 32;                      // arrival counters (max)
+constexpr int kBarStride = 32;                        // unsigned per counter: 128 bytes
+constexpr int kBarErr = kBarCounters * kBarStride;    // error flag, its own line
+constexpr int kBarWords = kBarErr + kBarStride;       // size of the barrier area
+
+template <int NC>
 __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned target, int* err) {
+  static_assert(NC >= 1 && NC <= kBarCounters, "");
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x < 64) {
+    const unsigned lane = threadIdx.x;
+    if (lane == 0)
+      __hip_atomic_fetch_add(bar + (blockIdx.x % NC) * kBarStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned spins = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (true) {
+      const unsigned v = lane < (unsigned)NC
+                             ? __hip_atomic_load(bar + lane * kBarStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                             : target;
+      if (__all(v >= target)) break;
       __builtin_amdgcn_s_sleep(2);
       if (++spins > kSpinLimit) {
-        __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0) __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
       if ((spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
@@ -167,6 +184,8 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
   for (int k = 0; k < EB; ++k) st[k] = c2(0.f, 0.f);
 
   unsigned nbar = 0;
+  constexpr int NC = G < kBarCounters ? G : kBarCounters;   // barrier counters (G is a power of two)
+  constexpr unsigned PER_C = G / NC;                          // arrivals per counter per barrier
   float2* Yg = a.Y;
   // element offsets fit in 32 bits (N <= 2^21 here); a uniform base plus a
   // 32-bit offset lets the compiler use scalar-base addressing
@@ -213,7 +232,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
     }
     __syncthreads();
     col_forward_store();
-    grid_barrier(a.bar, (++nbar) * G, a.err);
+    grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err);
   }
   __syncthreads();
 
@@ -338,7 +357,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
                lds[lp((2 * (i / (2 * N2)) + (i & 1)) * LDA + (i % (2 * N2)) / 2)]);
       }
     }
-    grid_barrier(a.bar, (++nbar) * G, a.err);
+    grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err);
 
     // ---- column pass: inverse columns, epilogue, forward columns -----------
     {
@@ -389,7 +408,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
     if (!last) {
       __syncthreads();
       col_forward_store();
-      grid_barrier(a.bar, (++nbar) * G, a.err);
+      grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err);
     }
   }
 
