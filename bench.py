@@ -10,8 +10,10 @@ seconds per step.
 
 Printed: one JSON line with the metric, the per-solver rates, the roofline of
 the dominant kernel (its algorithmic bytes per launch over its average launch
-duration, both measured here with HIP events on the launching stream) and the
-FP64 oracle timed on this host's cores on a bounded sample.
+duration, both measured here with HIP events on the launching stream; the
+measured HBM traffic per launch comes from the committed rocprofv3 counter
+record while the kernel sources match it) and the FP64 oracle timed on this
+host's cores on a bounded sample.
 """
 from __future__ import annotations
 
@@ -52,6 +54,27 @@ def kernel_bytes(n, d, ista_iters, admm_iters):
 
 
 ITER_BYTES_NOTE = "per iteration: 20n + 4m bytes (persistent) or 28n + 4m (two launches)"
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    record (FETCH_SIZE / WRITE_SIZE scaled by a copy-kernel calibration), or
+    None when the kernel sources have changed since it was taken."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    csrc = os.path.join(ROOT, "paper_1707_02244_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hpp")) + glob.glob(os.path.join(csrc, "*.hip"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    if h.hexdigest() != rec.get("kernel_sources_sha256"):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["traffic_bytes"]
 
 
 def main():
@@ -157,7 +180,7 @@ def main():
         dom = max(kern, key=lambda k: kern[k]["total_ms"])
         ach = kern[dom]["GBs"]
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                           "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                            "avg_launch_us": kern[dom]["avg_us"],
                            "bytes_per_launch": kern[dom]["bytes_per_launch"]}
         out["kernels"] = kern
@@ -285,7 +308,8 @@ def bench_2d(cs, torch, dev, steps, warmup, with_oracle):
     if kern:
         dom = max(kern, key=lambda k: kern[k]["avg_us"])
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": kern[dom]["GBs"], "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": kern[dom]["GBs"] / HBM_PEAK_GBS, "traffic": None}
+                           "unit": "GB/s", "frac": kern[dom]["GBs"] / HBM_PEAK_GBS,
+                           "traffic": measured_traffic(dom)}
     if with_oracle:
         from oracle import twod
         pr_lam = lam
