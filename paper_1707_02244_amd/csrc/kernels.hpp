@@ -33,11 +33,13 @@
 //   ADMM x-update (Alg. 2, with (A^T A + rho I)^{-1} applied by Woodbury:
 //     (A^T A + rho I)^{-1} = rho^{-1}[I - A^T (rho I + A A^T)^{-1} A], and
 //     A A^T is the m x m circulant with eigenvalues
-//     Lam_k' = (1/d) sum_class |c_hat|^2):
-//     Q_a = conj(c_a) Y_hat + rho X_a,  Q_b = conj(c_b) conj(Y_hat) + rho X_b,
-//     T = (sum_a c_a Q_a + conj(sum_b c_b Q_b)) / (d rho + sum |c|^2),
-//     X'_a = (Q_a - conj(c_a) T)/rho,  X'_b = (Q_b - conj(c_b) conj(T))/rho,
-//   where X is the spectrum of z - u.
+//     Lam_k' = (1/d) sum_class |c_hat|^2).  With Q_a = conj(c_a) Y_hat +
+//     rho X_a (X: the spectrum of z - u) the Woodbury form is
+//     X'_a = (Q_a - conj(c_a) T)/rho, T = (sum c_a Q_a + conj sum c_b Q_b) /
+//     (d rho + sum |c|^2); substituting Q gives the residual form used here,
+//     X'_a = X_a + conj(c_a) E,  X'_b = X_b + conj(c_b) conj(E),
+//     E = d (Y_hat - S) / (d rho + sum |c|^2),
+//   which avoids subtracting two nearly equal terms when Lam >> rho.
 // The time-domain steps (soft threshold, Eq. 4; ADMM's z and u updates) are
 // fused into pass B between its inverse and forward column transforms.
 #pragma once
@@ -292,25 +294,24 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
 #pragma unroll
         for (int l = 0; l < D2; ++l) { Va[l] = r; Vb[l] = rc; }
       } else {
+        // residual form of the Woodbury x-update (equal to (Q - conj(c) T) / rho):
+        // X' = X + conj(c) E, E = d (Y_hat - S) / (d rho + sum |c|^2)
         const float2 yk = gy[k];
-        float2 Qa[D2], Qb[D2];
-        const float2 ykc = cconj(yk);
         float2 ra_ = c2(0.f, 0.f), rb_ = c2(0.f, 0.f);
         float den = a.d_rho;   // d*rho + sum over the class of |c_hat|^2 = d (rho + Lam)
 #pragma unroll
         for (int l = 0; l < D2; ++l) {
-          Qa[l] = cadd(cconjmul(gca[k][l], yk), cscale(Xa[l], a.rho));
-          Qb[l] = cadd(cconjmul(gcb[k][l], ykc), cscale(Xb[l], a.rho));
-          ra_ = cadd(ra_, cmul(gca[k][l], Qa[l]));
-          rb_ = cadd(rb_, cmul(gcb[k][l], Qb[l]));
+          ra_ = cadd(ra_, cmul(gca[k][l], Xa[l]));
+          rb_ = cadd(rb_, cmul(gcb[k][l], Xb[l]));
           den += cabs2(gca[k][l]) + cabs2(gcb[k][l]);
         }
-        const float2 Tq = cscale(cadd(ra_, cconj(rb_)), 1.0f / den);
-        const float2 Tc = cconj(Tq);
+        const float2 S = cscale(cadd(ra_, cconj(rb_)), a.inv_d);
+        const float2 E = cscale(csub(yk, S), 1.0f / (den * a.inv_d));
+        const float2 Ec = cconj(E);
 #pragma unroll
         for (int l = 0; l < D2; ++l) {
-          Va[l] = cscale(csub(Qa[l], cconjmul(gca[k][l], Tq)), a.inv_rho);
-          Vb[l] = cscale(csub(Qb[l], cconjmul(gcb[k][l], Tc)), a.inv_rho);
+          Va[l] = cadd(Xa[l], cconjmul(gca[k][l], E));
+          Vb[l] = cadd(Xb[l], cconjmul(gcb[k][l], Ec));
         }
         if (a.res) {
           // residual of the updated x: S' = (sum c_a X'_a + conj sum c_b X'_b) / d

@@ -88,7 +88,13 @@ __device__ __forceinline__ void st_coh(float2* p, float2 v) {
 // reached its target; a workgroup barrier releases the other waves.  The wait
 // is bounded; hitting the bound sets the error flag, and a set flag ends every
 // later wait at once.
-constexpr int kBarCounters = 32;                      // arrival counters (max)
+#ifndef CS_BAR_COUNTERS
+#define CS_BAR_COUNTERS 256
+#endif
+#ifndef CS_BAR_SLEEP
+#define CS_BAR_SLEEP 2
+#endif
+constexpr int kBarCounters = CS_BAR_COUNTERS;         // arrival counters (max; one wave polls them)
 constexpr int kBarStride = 32;                        // unsigned per counter: 128 bytes
 constexpr int kBarErr = kBarCounters * kBarStride;    // error flag, its own line
 constexpr int kBarWords = kBarErr + kBarStride;       // size of the barrier area
@@ -104,11 +110,15 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned target, int
       __hip_atomic_fetch_add(bar + (blockIdx.x % NC) * kBarStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned spins = 0;
     while (true) {
-      const unsigned v = lane < (unsigned)NC
-                             ? __hip_atomic_load(bar + lane * kBarStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                             : target;
-      if (__all(v >= target)) break;
-      __builtin_amdgcn_s_sleep(2);
+      bool ok = true;
+#pragma unroll
+      for (int c0 = 0; c0 < NC; c0 += 64) {
+        const bool r = (c0 + lane >= (unsigned)NC) ||
+                       __hip_atomic_load(bar + (c0 + lane) * kBarStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
+        ok &= r;
+      }
+      if (__all(ok)) break;
+      __builtin_amdgcn_s_sleep(CS_BAR_SLEEP);
       if (++spins > kSpinLimit) {
         if (lane == 0) __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
@@ -315,24 +325,22 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
           Vb[l] = cconjmul(gcb[k][l], Ec);
         }
       } else {
-        float2 Qa[D2], Qb[D2];
-        const float2 yk = gy[k], ykc = cconj(gy[k]);
+        // residual form of the Woodbury x-update: X' = X + conj(c) E
         float2 r1 = c2(0.f, 0.f), r2 = c2(0.f, 0.f);
         float den = a.d_rho;
 #pragma unroll
         for (int l = 0; l < D2; ++l) {
-          Qa[l] = cadd(cconjmul(gca[k][l], yk), cscale(Xa[l], a.rho));
-          Qb[l] = cadd(cconjmul(gcb[k][l], ykc), cscale(Xb[l], a.rho));
-          r1 = cadd(r1, cmul(gca[k][l], Qa[l]));
-          r2 = cadd(r2, cmul(gcb[k][l], Qb[l]));
+          r1 = cadd(r1, cmul(gca[k][l], Xa[l]));
+          r2 = cadd(r2, cmul(gcb[k][l], Xb[l]));
           den += cabs2(gca[k][l]) + cabs2(gcb[k][l]);
         }
-        const float2 Tq = cscale(cadd(r1, cconj(r2)), 1.0f / den);
-        const float2 Tc = cconj(Tq);
+        const float2 S = cscale(cadd(r1, cconj(r2)), a.inv_d);
+        const float2 E = cscale(csub(gy[k], S), 1.0f / (den * a.inv_d));
+        const float2 Ec = cconj(E);
 #pragma unroll
         for (int l = 0; l < D2; ++l) {
-          Va[l] = cscale(csub(Qa[l], cconjmul(gca[k][l], Tq)), a.inv_rho);
-          Vb[l] = cscale(csub(Qb[l], cconjmul(gcb[k][l], Tc)), a.inv_rho);
+          Va[l] = cadd(Xa[l], cconjmul(gca[k][l], E));
+          Vb[l] = cadd(Xb[l], cconjmul(gcb[k][l], Ec));
         }
       }
 #pragma unroll
