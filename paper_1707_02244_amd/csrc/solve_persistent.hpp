@@ -6,16 +6,16 @@
 // the fused time-domain epilogue.  One launch runs all iterations, with a grid
 // barrier between the row pass and the column pass.  Each workgroup owns fixed
 // work for the whole solve:
-//   - AI row pairs {w, N1 - w}, w = g + i*G (the row pass); their c_hat and
-//     y_hat entries are re-read each iteration (they stay in the XCD's L2,
-//     since workgroup g runs on the same XCD every iteration);
+//   - AI row pairs {w, N1 - w}, w = g + i*G (the row pass); the c_hat and
+//     y_hat entries of its alias classes are loaded into registers once per
+//     solve and stay there;
 //   - one block of CB adjacent columns (the column pass); it keeps the
 //     time-domain state of those columns (ISTA: the iterate x; ADMM: the
 //     scaled dual u) in registers.
-// The state never leaves the CU between iterations: HBM sees the spectrum
-// buffer Y (read and written by both passes, 16n bytes per iteration) plus the
-// L2-resident c_hat / y_hat reads.  All twiddle tables (FFT stages, four-step,
-// real split) are loaded into LDS once per launch.
+// The state never leaves the CU between iterations: HBM sees only the
+// spectrum buffer Y (read and written by both passes, 16n bytes per
+// iteration).  All twiddle tables (FFT stages, four-step, real split) are
+// loaded into LDS once per launch.
 //
 // Y interleaves each mirror row pair: element (k1, j2) of the four-step
 // intermediate lives at Y[(w * N2 + j2) * 2 + s], where pair w holds rows w
@@ -246,13 +246,32 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
   }
   __syncthreads();
 
+  // class operands (c_hat, y_hat at this thread's alias classes) are
+  // constant over the solve: load them once
+  float2 gca[GPT][D2], gcb[GPT][D2], gy[GPT];
+  {
+#pragma unroll
+    for (int k = 0; k < GPT; ++k) {
+      const unsigned q = tid + k * T;
+      if (q < (unsigned)ncls) {
+        const Cls c = decode(q);
+#pragma unroll
+        for (int l = 0; l < D2; ++l) {
+          const int p = c.k2 + l * M;
+          const int qq = (c.mode == 1) ? ((N2 - p) & (N2 - 1)) : (N2 - 1 - p);
+          gca[k][l] = a.chat[(unsigned)c.rowa * N2 + p];
+          gcb[k][l] = (c.mode == 1 && p == 0) ? a.chat[N] : a.chat[(unsigned)c.rowb * N2 + qq];
+        }
+        gy[k] = a.yhat[(unsigned)c.rowa * N2 + c.k2];
+      }
+    }
+  }
   for (int t = 1; t <= a.iters; ++t) {
     // keep per-thread index arithmetic inside the iteration: hoisting it out
     // of the loop keeps dozens of addresses live and forces spills
     asm volatile("" : "+v"(tid));
     // ---- row pass: forward rows, alias-class update, inverse rows ----------
-    // Issue the row loads and this thread's c_hat / y_hat loads together.
-    float2 gca[GPT][D2], gcb[GPT][D2], gy[GPT];
+    // Issue every row load before the first LDS store.
     {
       float2 rv[EA];
       const bool zero_in = (t == 1) && !(ALG == 1 && a.warm);
@@ -263,21 +282,6 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
           // pair i / (2 N2) of this workgroup, one contiguous block
           const unsigned w = g + (i / (2 * N2)) * G;
           rv[k] = zero_in ? c2(0.f, 0.f) : ld_coh(&Yg[w * (2 * N2) + i % (2 * N2)]);
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < GPT; ++k) {
-        const unsigned q = tid + k * T;
-        if (q < (unsigned)ncls) {
-          const Cls c = decode(q);
-#pragma unroll
-          for (int l = 0; l < D2; ++l) {
-            const int p = c.k2 + l * M;
-            const int qq = (c.mode == 1) ? ((N2 - p) & (N2 - 1)) : (N2 - 1 - p);
-            gca[k][l] = a.chat[(unsigned)c.rowa * N2 + p];
-            gcb[k][l] = (c.mode == 1 && p == 0) ? a.chat[N] : a.chat[(unsigned)c.rowb * N2 + qq];
-          }
-          gy[k] = a.yhat[(unsigned)c.rowa * N2 + c.k2];
         }
       }
 #pragma unroll
