@@ -26,7 +26,7 @@ constexpr int kBMinLogN = 9;                         // n = 2^10 ..
 constexpr int kBMaxLogN = 17;                        // .. 2^18
 constexpr int kBMaxN1 = 256;
 constexpr int kBMaxN2 = 512;
-constexpr int kBLds = kBPoints + 16 * kPadA + 64;    // rows carry kPadA padding each
+constexpr int kBLds = lds_rows(kBPoints + 16 * kPadA) + 64;   // rows carry kPadA padding each
 
 // Everything a workgroup needs for one signal (built on the host).
 struct BatchSig {
@@ -64,7 +64,7 @@ __device__ __forceinline__ void batch_rows(const BatchSig& s, float2* table, int
   constexpr int M = N2 / D2;
   constexpr int NCLS = (OP == A_ISTA) ? AI * M + 1 : 1;
   constexpr int GPT = (NCLS + T - 1) / T;
-  static_assert(RA * LDA <= kBLds, "row step exceeds the LDS buffer");
+  static_assert(lds_rows(RA * LDA) <= kBLds, "row step exceeds the LDS buffer");
   const int ng0 = (w0 == 0) ? (M + 1) : M;
   const int ncls = ng0 + (AI - 1) * M;
   auto row_of = [&](unsigned slot) -> unsigned {
@@ -111,7 +111,7 @@ __device__ __forceinline__ void batch_rows(const BatchSig& s, float2* table, int
 #pragma unroll
     for (int k = 0; k < EA; ++k) {
       const unsigned i = tid + k * T;
-      if (FA || i < RA * N2) lds[lp((i / N2) * LDA + (i % N2))] = rv[k];
+      if (FA || i < RA * N2) lds[lpr((i / N2) * LDA + (i % N2))] = rv[k];
     }
   }
   __syncthreads();
@@ -128,8 +128,8 @@ __device__ __forceinline__ void batch_rows(const BatchSig& s, float2* table, int
       if (w) { qs = slot ^ 1; qp = N2 - 1 - p; }
       else if ((slot & 1) == 0) { qs = slot; qp = (N2 - p) & (N2 - 1); }
       else { qs = slot; qp = N2 - 1 - p; }
-      const float2 za = lds[lp(slot * LDA + p)];
-      const float2 zbc = cconj(lds[lp(qs * LDA + qp)]);
+      const float2 za = lds[lpr(slot * LDA + p)];
+      const float2 zbc = cconj(lds[lpr(qs * LDA + qp)]);
       const float2 wt = cmul(s.twk1[row], s.twp[p]);
       const float2 P = cscale(cadd(za, zbc), 0.5f);
       const float2 Q = cscale(cmulmi(csub(za, zbc)), 0.5f);
@@ -153,8 +153,8 @@ __device__ __forceinline__ void batch_rows(const BatchSig& s, float2* table, int
         const int p = k2 + l * M;
         const int qq = (mode == 1) ? ((N2 - p) & (N2 - 1)) : (N2 - 1 - p);
         gw[l] = cmul(wk1, s.twp[p]);
-        const float2 za = lds[lp(sa * LDA + p)];
-        const float2 zbc = cconj(lds[lp(sb * LDA + qq)]);
+        const float2 za = lds[lpr(sa * LDA + p)];
+        const float2 zbc = cconj(lds[lpr(sb * LDA + qq)]);
         const float2 P = cscale(cadd(za, zbc), 0.5f);
         const float2 Q = cscale(cmulmi(csub(za, zbc)), 0.5f);
         const float2 wq = cmul(gw[l], Q);
@@ -176,8 +176,8 @@ __device__ __forceinline__ void batch_rows(const BatchSig& s, float2* table, int
         const float2 vbc = cconj(cconjmul(gcb[k][l], Ec));
         const float2 E_ = cscale(cadd(Va, vbc), inv_n);
         const float2 O_ = cscale(cmulc(csub(Va, vbc), gw[l]), inv_n);
-        lds[lp(sa * LDA + p)] = cadd(E_, cmuli(O_));
-        if (write_b) lds[lp(sb * LDA + qq)] = cconj(csub(E_, cmuli(O_)));
+        lds[lpr(sa * LDA + p)] = cadd(E_, cmuli(O_));
+        if (write_b) lds[lpr(sb * LDA + qq)] = cconj(csub(E_, cmuli(O_)));
       }
     }
     __syncthreads();
@@ -185,7 +185,7 @@ __device__ __forceinline__ void batch_rows(const BatchSig& s, float2* table, int
 #pragma unroll
     for (int k = 0; k < EA; ++k) {
       const unsigned i = tid + k * T;
-      if (FA || i < RA * N2) s.Y[row_of(i / N2) * N2 + (i % N2)] = lds[lp((i / N2) * LDA + (i % N2))];
+      if (FA || i < RA * N2) s.Y[row_of(i / N2) * N2 + (i % N2)] = lds[lpr((i / N2) * LDA + (i % N2))];
     }
   }
 }

@@ -44,12 +44,24 @@ constexpr int stage_radix(int L, int NS) {
   return (p % 3 == 0) ? 8 : ((p % 3 == 2) ? 4 : (p == 1 ? 2 : 4));
 }
 
-// LDS slot of flat index x (identity).  Bank swizzles and per-32 padding
+// LDS slot of flat index x in interleaved (column) buffers: identity.
+// Bank swizzles and per-32 padding applied through a per-access function
 // were measured slower on gfx950: they stop the compiler from folding
-// constant offsets into ds_read2 / ds_write2 pairs, and the extra LDS
-// instructions cost more than the bank conflicts they remove.
+// constant offsets into paired ds_read2 / ds_write2 accesses.
 __device__ __forceinline__ unsigned lp(unsigned x) { return x; }
 constexpr int lds_padded(int n) { return n; }
+
+#ifndef CS_ROW_PAD
+#define CS_ROW_PAD 1
+#endif
+// Row buffers (sequences stored one after another): with CS_ROW_PAD one pad
+// slot follows every 32 slots, which moves the strided stores of the early
+// Stockham stages off the banks they would otherwise share.  The FFT stages
+// compute one padded base per butterfly and add compile-time offsets (valid
+// for power-of-two radices, spans and row lengths that are multiples of 32).
+__device__ __forceinline__ unsigned lpr(unsigned x) { return CS_ROW_PAD ? x + (x >> 5) : x; }
+constexpr int lds_rows(int n) { return CS_ROW_PAD ? n + n / 32 + 1 : n; }
+constexpr unsigned prc(unsigned x) { return CS_ROW_PAD ? x + x / 32 : x; }
 
 // multiply by the primitive 8th root of unity W8^q (q = 1, 3), forward sign
 // exp(-i pi q / 4) or inverse sign exp(+i pi q / 4).
@@ -153,7 +165,7 @@ __device__ __forceinline__ void dft(float2* v) {
 template <bool ILV, int B, int LD>
 __device__ __forceinline__ unsigned lds_addr(unsigned b, unsigned i) {
   if constexpr (ILV) return lp(i * B + b);
-  else return lp(b * LD + i);
+  else return lpr(b * LD + i);
 }
 
 template <int L, int B, int T, bool INV, bool ILV, int LD, int NS, int R>
@@ -163,14 +175,24 @@ __device__ __forceinline__ void stockham_stage(float2* __restrict__ buf,
   constexpr int NBF = B * Q;        // butterflies per stage
   constexpr int PER = (NBF + T - 1) / T;
   float2 v[PER][R];
+  // explicit padded bases need rows that start on 32-slot blocks; otherwise
+  // the per-access map lds_addr (the same mapping) is used
+  constexpr bool PADR = CS_ROW_PAD && !ILV && (B == 1 || LD % 32 == 0);
+  constexpr unsigned LDP = prc(LD);   // padded row stride
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
     const unsigned i = tid + p * T;
     if (NBF % T == 0 || i < NBF) {
       const unsigned b = ILV ? (i % B) : (i / Q);
       const unsigned j = ILV ? (i / B) : (i % Q);
+      if constexpr (PADR) {
+        const unsigned rb = b * LDP + lpr(j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[p][r] = buf[lds_addr<ILV, B, LD>(b, j + r * Q)];
+        for (int r = 0; r < R; ++r) v[p][r] = buf[rb + prc(r * Q)];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[p][r] = buf[lds_addr<ILV, B, LD>(b, j + r * Q)];
+      }
     }
   }
   __syncthreads();
@@ -209,8 +231,14 @@ __device__ __forceinline__ void stockham_stage(float2* __restrict__ buf,
       }
       dft<R, INV>(v[p]);
       const unsigned base = (j - k) * R + k;
+      if constexpr (PADR) {
+        const unsigned wb = b * LDP + lpr(base);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lds_addr<ILV, B, LD>(b, base + r * NS)] = v[p][r];
+        for (int r = 0; r < R; ++r) buf[wb + prc(r * NS)] = v[p][r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[lds_addr<ILV, B, LD>(b, base + r * NS)] = v[p][r];
+      }
     }
   }
   __syncthreads();

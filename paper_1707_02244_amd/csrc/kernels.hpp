@@ -50,7 +50,7 @@ namespace cs {
 
 constexpr int kThreads = 256;
 constexpr int kColsPerBlock = 8;   // pass B: adjacent columns per workgroup (64 B runs)
-constexpr int kPadA = 4;   // pass A: float2 padding between rows
+constexpr int kPadA = CS_ROW_PAD ? 0 : 4;   // pass A: float2 padding between rows
 
 enum OpA : int {
   A_ISTA = 0,   // ISTA frequency update (alias classes)
@@ -216,7 +216,7 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const int i = tid + k * T;
-    if ((2 * N2) % T == 0 || i < 2 * N2) lds[lp((i / N2) * LD + (i % N2))] = rv[k];
+    if ((2 * N2) % T == 0 || i < 2 * N2) lds[lpr((i / N2) * LD + (i % N2))] = rv[k];
   }
   __syncthreads();
   lds_fft<N2, 2, T, false, false, LD>(lds, tws, tid);
@@ -247,8 +247,8 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
         const int p = k2 + l * M;
         const int q = (mode == 1) ? ((N2 - p) & (N2 - 1)) : (N2 - 1 - p);
         pa[l] = p; qb[l] = q;
-        const float2 za = lds[lp(sa * LD + p)];
-        const float2 zbc = cconj(lds[lp(sb * LD + q)]);
+        const float2 za = lds[lpr(sa * LD + p)];
+        const float2 zbc = cconj(lds[lpr(sb * LD + q)]);
         const float2 P = cscale(cadd(za, zbc), 0.5f);
         const float2 Q = cscale(cmulmi(csub(za, zbc)), 0.5f);
         const float2 wq = cmul(gw[k][l], Q);
@@ -327,8 +327,8 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
         const float2 vbc = cconj(Vb[l]);
         const float2 E_ = cscale(cadd(Va[l], vbc), a.inv_n);
         const float2 O_ = cscale(cmulc(csub(Va[l], vbc), gw[k][l]), a.inv_n);
-        lds[lp(sa * LD + pa[l])] = cadd(E_, cmuli(O_));
-        if (write_b) lds[lp(sb * LD + qb[l])] = cconj(csub(E_, cmuli(O_)));
+        lds[lpr(sa * LD + pa[l])] = cadd(E_, cmuli(O_));
+        if (write_b) lds[lpr(sb * LD + qb[l])] = cconj(csub(E_, cmuli(O_)));
       }
     }
   } else {
@@ -345,8 +345,8 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
       const int rowb = (mode == 0) ? (N1 - w) : rowa;
       const int q = (mode == 1) ? ((N2 - p) & (N2 - 1)) : (N2 - 1 - p);
       const bool write_b = !(mode == 1 && (p == 0 || p == (N2 >> 1)));
-      const float2 za = lds[lp(sa * LD + p)];
-      const float2 zb = lds[lp(sb * LD + q)];
+      const float2 za = lds[lpr(sa * LD + p)];
+      const float2 zb = lds[lpr(sb * LD + q)];
       const float2 wt = cmul(a.twk1[rowa], a.twp[p]);
       const float2 zbc = cconj(zb);
       const float2 P = cscale(cadd(za, zbc), 0.5f);
@@ -367,8 +367,8 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
         const float2 vbc = cconj(Vb);
         const float2 E_ = cscale(cadd(Va, vbc), a.inv_n);
         const float2 O_ = cscale(cmulc(csub(Va, vbc), wt), a.inv_n);
-        lds[lp(sa * LD + p)] = cadd(E_, cmuli(O_));
-        if (write_b) lds[lp(sb * LD + q)] = cconj(csub(E_, cmuli(O_)));
+        lds[lpr(sa * LD + p)] = cadd(E_, cmuli(O_));
+        if (write_b) lds[lpr(sb * LD + q)] = cconj(csub(E_, cmuli(O_)));
       }
     }
   }
@@ -386,7 +386,7 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
       const int i = tid + k * T;
       if ((2 * N2) % T == 0 || i < 2 * N2) {
         const int s = i / N2, p = i % N2;
-        a.Y[(size_t)(s ? rb : ra) * N2 + p] = lds[lp(s * LD + p)];
+        a.Y[(size_t)(s ? rb : ra) * N2 + p] = lds[lpr(s * LD + p)];
       }
     }
   }
@@ -399,8 +399,8 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
 template <int N2, int OP, int D2>
 __global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
   constexpr int LD = N2 + kPadA;
-  constexpr bool TW_LDS = (lds_padded(2 * LD) + N2) * 8 <= 160 * 1024 - 1024;
-  __shared__ float2 lds[lds_padded(2 * LD)];
+  constexpr bool TW_LDS = (lds_rows(2 * LD) + N2) * 8 <= 160 * 1024 - 1024;
+  __shared__ float2 lds[lds_rows(2 * LD)];
   __shared__ float2 tws_l[TW_LDS ? N2 : 1];
   if constexpr (TW_LDS) {
     for (unsigned i = threadIdx.x; i < N2; i += kThreads) tws_l[i] = a.tw2[i];

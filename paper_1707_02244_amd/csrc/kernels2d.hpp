@@ -53,7 +53,7 @@ namespace cs {
 #define CS_ROW2_TWLDS 1  // row pass: FFT twiddles staged in LDS (else read from the global table)
 #endif
 constexpr int kRows2 = CS_ROWS2;   // image rows per row-pass workgroup (8: 64-byte runs of T)
-constexpr int kPad2 = 4;   // float2 padding between LDS rows / columns
+constexpr int kPad2 = CS_ROW_PAD ? 0 : 4;   // float2 padding between LDS rows / columns
 
 enum OpC2 : int {
   C2_ISTA = 0,     // ISTA class update (step spectrum)
@@ -124,12 +124,12 @@ __global__ __launch_bounds__(col2_threads<R>(), CS_COL2_MINW) void k2_col(Col2Ar
   constexpr int LD = R + kPad2;
   constexpr int NE = 2 * R;
   constexpr int EPT = (NE + T - 1) / T;
-  constexpr bool TW_LDS = (lds_padded(2 * LD) + R) * 8 <= 64 * 1024;
+  constexpr bool TW_LDS = (lds_rows(2 * LD) + R) * 8 <= 64 * 1024;
   constexpr bool GROUP = (OP == C2_ISTA || OP == C2_ADMM || OP == C2_RES);
   constexpr bool TABLE = (OP == C2_SPEC || OP == C2_SPECMUL || OP == C2_YHAT);
   constexpr bool WRITE_BACK = (OP == C2_ISTA || OP == C2_ADMM || OP == C2_MUL || OP == C2_MULC);
   constexpr int HR = R / 2;
-  __shared__ float2 lds[lds_padded(2 * LD)];
+  __shared__ float2 lds[lds_rows(2 * LD)];
   __shared__ float2 tws_l[TW_LDS ? R : 1];
   const unsigned tid = threadIdx.x;
   const int w = blockIdx.x;
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(col2_threads<R>(), CS_COL2_MINW) void k2_col(Col2Ar
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const unsigned i = tid + k * T;
-    if (NE % T == 0 || i < NE) lds[lp((i & 1) * LD + (i >> 1))] = v[k];
+    if (NE % T == 0 || i < NE) lds[lpr((i & 1) * LD + (i >> 1))] = v[k];
   }
   __syncthreads();
   lds_fft<R, 2, T, false, false, LD>(lds, tws, tid);
@@ -188,8 +188,8 @@ __global__ __launch_bounds__(col2_threads<R>(), CS_COL2_MINW) void k2_col(Col2Ar
       const bool self = (w == 0) && (k1 == 0 || k1 == R / 4);
       const float2 wp = a.twc[slot ? (H >> 1) : w];
       const int a0 = k1, a1 = k1 + HR, b0 = (R - k1) & (R - 1), b1 = HR - k1;
-      const float2 za0 = lds[lp(sa * LD + a0)], za1 = lds[lp(sa * LD + a1)];
-      const float2 zb0 = cconj(lds[lp(sb * LD + b0)]), zb1 = cconj(lds[lp(sb * LD + b1)]);
+      const float2 za0 = lds[lpr(sa * LD + a0)], za1 = lds[lpr(sa * LD + a1)];
+      const float2 zb0 = cconj(lds[lpr(sb * LD + b0)]), zb1 = cconj(lds[lpr(sb * LD + b1)]);
       const float2 E0 = cscale(cadd(za0, zb0), 0.5f), O0 = cscale(cmulmi(csub(za0, zb0)), 0.5f);
       const float2 E1 = cscale(cadd(za1, zb1), 0.5f), O1 = cscale(cmulmi(csub(za1, zb1)), 0.5f);
       const float2 wO0 = cmul(wp, O0), wO1 = cmul(wp, O1);
@@ -226,11 +226,11 @@ __global__ __launch_bounds__(col2_threads<R>(), CS_COL2_MINW) void k2_col(Col2Ar
       // inverse split, scaled by 1/(R C)
       const float2 Ea = cscale(cadd(X[0], X[2]), a.inv_n), Oa = cscale(cmulc(csub(X[0], X[2]), wp), a.inv_n);
       const float2 Eb = cscale(cadd(X[1], X[3]), a.inv_n), Ob = cscale(cmulc(csub(X[1], X[3]), wp), a.inv_n);
-      lds[lp(sa * LD + a0)] = cadd(Ea, cmuli(Oa));
-      lds[lp(sa * LD + a1)] = cadd(Eb, cmuli(Ob));
+      lds[lpr(sa * LD + a0)] = cadd(Ea, cmuli(Oa));
+      lds[lpr(sa * LD + a1)] = cadd(Eb, cmuli(Ob));
       if (!self) {
-        lds[lp(sb * LD + b0)] = cconj(csub(Ea, cmuli(Oa)));
-        lds[lp(sb * LD + b1)] = cconj(csub(Eb, cmuli(Ob)));
+        lds[lpr(sb * LD + b0)] = cconj(csub(Ea, cmuli(Oa)));
+        lds[lpr(sb * LD + b1)] = cconj(csub(Eb, cmuli(Ob)));
       }
     }
     if (a.res) {
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(col2_threads<R>(), CS_COL2_MINW) void k2_col(Col2Ar
       const int b = (R - k1) & (R - 1);
       const bool self = (w == 0) && (k1 == 0 || k1 == HR);
       const float2 wp = a.twc[p];
-      const float2 za = lds[lp(sa * LD + k1)], zbc = cconj(lds[lp(sb * LD + b)]);
+      const float2 za = lds[lpr(sa * LD + k1)], zbc = cconj(lds[lpr(sb * LD + b)]);
       const float2 E = cscale(cadd(za, zbc), 0.5f), O = cscale(cmulmi(csub(za, zbc)), 0.5f);
       const float2 wO = cmul(wp, O);
       const float2 Xlo = cadd(E, wO), Xhi = csub(E, wO);
@@ -271,8 +271,8 @@ __global__ __launch_bounds__(col2_threads<R>(), CS_COL2_MINW) void k2_col(Col2Ar
         const float2 Vhi = OP == C2_MUL ? cmul(ghi, Xhi) : cconjmul(ghi, Xhi);
         const float2 E_ = cscale(cadd(Vlo, Vhi), a.inv_n);
         const float2 O_ = cscale(cmulc(csub(Vlo, Vhi), wp), a.inv_n);
-        lds[lp(sa * LD + k1)] = cadd(E_, cmuli(O_));
-        if (!self) lds[lp(sb * LD + b)] = cconj(csub(E_, cmuli(O_)));
+        lds[lpr(sa * LD + k1)] = cadd(E_, cmuli(O_));
+        if (!self) lds[lpr(sb * LD + b)] = cconj(csub(E_, cmuli(O_)));
       }
     }
   }
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(col2_threads<R>(), CS_COL2_MINW) void k2_col(Col2Ar
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       const unsigned i = tid + k * T;
-      if (NE % T == 0 || i < NE) a.T[(size_t)w * NE + i] = lds[lp((i & 1) * LD + (i >> 1))];
+      if (NE % T == 0 || i < NE) a.T[(size_t)w * NE + i] = lds[lpr((i & 1) * LD + (i >> 1))];
     }
   }
 }
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(row2_threads<H>(), CS_ROW2_MINW) void k2_row(Row2Ar
   constexpr int CH = EPT < 8 ? EPT : 8;
   constexpr bool FULL = (NE % T) == 0;
   constexpr bool HAS_INV = (MODE == R2_ISTA || MODE == R2_ADMM || MODE == R2_OUT_ALL || MODE == R2_OUT_DEC);
-  __shared__ float2 lds[lds_padded(RW * LD)];
+  __shared__ float2 lds[lds_rows(RW * LD)];
   __shared__ float2 tws_l[CS_ROW2_TWLDS ? H : 1];
   const float2* tws = CS_ROW2_TWLDS ? tws_l : a.twH;
   const unsigned tid = threadIdx.x;
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(row2_threads<H>(), CS_ROW2_MINW) void k2_row(Row2Ar
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const unsigned i = tid + (k0 + k) * T;
-        if (FULL || i < NE) lds[lp(t_lds(i))] = v[k];
+        if (FULL || i < NE) lds[lpr(t_lds(i))] = v[k];
       }
     }
     __syncthreads();
@@ -355,13 +355,13 @@ __global__ __launch_bounds__(row2_threads<H>(), CS_ROW2_MINW) void k2_row(Row2Ar
           if (FULL || i < NE) {
             const unsigned li = (i / H) * LD + (i % H);
             if constexpr (MODE == R2_ISTA) {
-              const float2 vv = cadd(sv[k], lds[lp(li)]);
+              const float2 vv = cadd(sv[k], lds[lpr(li)]);
               const float2 x = c2(soft(vv.x, a.thr), soft(vv.y, a.thr));
               l1_acc += fabsf(x.x) + fabsf(x.y);
               st[i] = x;
-              lds[lp(li)] = x;
+              lds[lpr(li)] = x;
             } else {
-              const float2 x = lds[lp(li)];
+              const float2 x = lds[lpr(li)];
               l1_acc += fabsf(x.x) + fabsf(x.y);
               const float2 xu = cadd(x, sv[k]);
               const float2 z = c2(soft(xu.x, a.thr), soft(xu.y, a.thr));
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(row2_threads<H>(), CS_ROW2_MINW) void k2_row(Row2Ar
                 reinterpret_cast<float2*>(a.out0)[tbase + i] = x;
                 reinterpret_cast<float2*>(a.out1)[tbase + i] = z;
               } else {
-                lds[lp(li)] = csub(z, u1);
+                lds[lpr(li)] = csub(z, u1);
               }
             }
           }
@@ -384,13 +384,13 @@ __global__ __launch_bounds__(row2_threads<H>(), CS_ROW2_MINW) void k2_row(Row2Ar
       fwd = !a.last;
     } else if constexpr (MODE == R2_OUT_ALL) {
       for (unsigned i = tid; i < NE; i += T)
-        reinterpret_cast<float2*>(a.out0)[tbase + i] = lds[lp((i / H) * LD + (i % H))];
+        reinterpret_cast<float2*>(a.out0)[tbase + i] = lds[lpr((i / H) * LD + (i % H))];
       fwd = false;
     } else {  // R2_OUT_DEC: even rows, even columns (the real parts)
       for (unsigned i = tid; i < NE; i += T) {
         const unsigned c = i / H, j = i % H;
         const int r = r0 + int(c);
-        if ((r & 1) == 0) a.out0[(size_t)(r >> 1) * H + j] = lds[lp(c * LD + j)].x;
+        if ((r & 1) == 0) a.out0[(size_t)(r >> 1) * H + j] = lds[lpr(c * LD + j)].x;
       }
       fwd = false;
     }
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(row2_threads<H>(), CS_ROW2_MINW) void k2_row(Row2Ar
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const unsigned i = tid + (k0 + k) * T;
-        if (FULL || i < NE) lds[lp((i / H) * LD + (i % H))] = v[k];
+        if (FULL || i < NE) lds[lpr((i / H) * LD + (i % H))] = v[k];
       }
     }
     __syncthreads();
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(row2_threads<H>(), CS_ROW2_MINW) void k2_row(Row2Ar
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const unsigned i = tid + k * T;
-    if (FULL || i < NE) a.T[t_off(i)] = lds[lp(t_lds(i))];
+    if (FULL || i < NE) a.T[t_off(i)] = lds[lpr(t_lds(i))];
   }
 }
 

@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
   constexpr int RA = 2 * AI;                 // rows held in the row pass
   constexpr int NA = RA * LDA;
   constexpr int NEB = N1 * CB;
-  constexpr int NL = NA > NEB ? NA : NEB;
+  constexpr int NL = lds_rows(NA) > NEB ? lds_rows(NA) : NEB;
   constexpr int EA = (RA * N2 + T - 1) / T;  // row-pass elements per thread
   constexpr bool FA = (RA * N2) % T == 0;
   constexpr int EB = (NEB + T - 1) / T;      // column-pass elements per thread
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
       for (int k = 0; k < EA; ++k) {
         const unsigned i = tid + k * T;
         // slot 2 * pair + side, position j2
-        if (FA || i < RA * N2) lds[lp((2 * (i / (2 * N2)) + (i & 1)) * LDA + (i % (2 * N2)) / 2)] = rv[k];
+        if (FA || i < RA * N2) lds[lpr((2 * (i / (2 * N2)) + (i & 1)) * LDA + (i % (2 * N2)) / 2)] = rv[k];
       }
     }
     __syncthreads();
@@ -307,8 +307,8 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
         const int p = k2 + l * M;
         const int qq = (mode == 1) ? ((N2 - p) & (N2 - 1)) : (N2 - 1 - p);
         gw[l] = cmul(wk1, tp[p]);
-        const float2 za = lds[lp(sa * LDA + p)];
-        const float2 zbc = cconj(lds[lp(sb * LDA + qq)]);
+        const float2 za = lds[lpr(sa * LDA + p)];
+        const float2 zbc = cconj(lds[lpr(sb * LDA + qq)]);
         const float2 P = cscale(cadd(za, zbc), 0.5f);
         const float2 Q = cscale(cmulmi(csub(za, zbc)), 0.5f);
         const float2 wq = cmul(gw[l], Q);
@@ -354,8 +354,8 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
         const float2 vbc = cconj(Vb[l]);
         const float2 E_ = cscale(cadd(Va[l], vbc), a.inv_n);
         const float2 O_ = cscale(cmulc(csub(Va[l], vbc), gw[l]), a.inv_n);
-        lds[lp(sa * LDA + p)] = cadd(E_, cmuli(O_));
-        if (write_b) lds[lp(sb * LDA + qq)] = cconj(csub(E_, cmuli(O_)));
+        lds[lpr(sa * LDA + p)] = cadd(E_, cmuli(O_));
+        if (write_b) lds[lpr(sb * LDA + qq)] = cconj(csub(E_, cmuli(O_)));
       }
     }
     __syncthreads();
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
       if (FA || i < RA * N2) {
         const unsigned w = g + (i / (2 * N2)) * G;
         st_coh(&Yg[w * (2 * N2) + i % (2 * N2)],
-               lds[lp((2 * (i / (2 * N2)) + (i & 1)) * LDA + (i % (2 * N2)) / 2)]);
+               lds[lpr((2 * (i / (2 * N2)) + (i & 1)) * LDA + (i % (2 * N2)) / 2)]);
       }
     }
     grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err);

@@ -33,8 +33,8 @@ struct UStride {
 template <int N2, int OP, int D2>
 __global__ __launch_bounds__(kThreads) void k_urow(PassAArgs a, UStride st) {
   constexpr int LD = N2 + kPadA;
-  constexpr bool TW_LDS = (lds_padded(2 * LD) + N2) * 8 <= 160 * 1024 - 1024;
-  __shared__ float2 lds[lds_padded(2 * LD)];
+  constexpr bool TW_LDS = (lds_rows(2 * LD) + N2) * 8 <= 160 * 1024 - 1024;
+  __shared__ float2 lds[lds_rows(2 * LD)];
   __shared__ float2 tws_l[TW_LDS ? N2 : 1];
   const long long b = blockIdx.y;
   a.Y += b * st.Y;
