@@ -1,5 +1,8 @@
-// Unrolled ISTA over a batch of signals that share one sensing operator:
-// forward with per-iteration parameters and a checkpointed reverse pass.
+// Row and column passes over a batch of equal-length signals (grid y =
+// signal).  Used by the unrolled ISTA (signals sharing one sensing operator:
+// forward with per-iteration parameters and a checkpointed reverse pass) and
+// by the batched solver for groups of long signals of one length (each with
+// its own c_hat, tau and lambda).
 //
 // The row and column passes of kernels.hpp run with a second grid dimension
 // over the signals of the batch; each signal has its own spectrum buffer,
@@ -28,6 +31,9 @@ struct UStride {
   long long out0;   // column-pass output (float)
   long long rv, rd, xbar, vbar;   // records and adjoint state (float)
   long long part;   // partial sums (double): per signal, then + blockIdx.x
+  long long chat;   // c_hat table (float2): 0 when the signals share c
+  long long par;    // per-signal parameters tau_dev / lam_dev (float): 0 when
+                    //   they are per iteration (indexed by t) instead
 };
 
 template <int N2, int OP, int D2>
@@ -38,6 +44,8 @@ __global__ __launch_bounds__(kThreads) void k_urow(PassAArgs a, UStride st) {
   __shared__ float2 tws_l[TW_LDS ? N2 : 1];
   const long long b = blockIdx.y;
   a.Y += b * st.Y;
+  a.chat += b * st.chat;
+  if (a.tau_dev) a.tau_dev += b * st.par;
   if (a.yhat) a.yhat += b * st.yhat;
   if (a.ybar) a.ybar += b * st.ybar;
   if (a.table) a.table += b * st.table;
@@ -62,6 +70,8 @@ __global__ __launch_bounds__(kThreads) void k_ucol(PassBArgs a, UStride st) {
   if (a.xbar) a.xbar += b * st.xbar;
   if (a.vbar) a.vbar += b * st.vbar;
   if (a.part) a.part += b * st.part + blockIdx.x;
+  if (a.tau_dev) a.tau_dev += b * st.par;
+  if (a.lam_dev) a.lam_dev += b * st.par;
   for (unsigned i = threadIdx.x; i < N1; i += kThreads) tws[i] = a.tw1[i];
   __syncthreads();
   colpass<N1, MODE, kThreads>(a, blockIdx.x, lds, tws, threadIdx.x);

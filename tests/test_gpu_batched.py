@@ -110,3 +110,31 @@ def test_batched_rejects_bad_sizes():
         cs.ista_solve_batched(np.array([1 << 9]), 4, g(np.ones(1 << 9)), g(np.ones(1 << 7)), g(lam), g(tau), 3)
     with pytest.raises(cs.CsError):
         cs.ista_solve_batched(ns, 16, g(c), g(np.ones(len(c) // 16)), g(lam), g(tau), 3)
+
+
+@pytest.mark.parametrize("d", [2, 8])
+def test_batched_length_groups_vs_oracle(d):
+    """Several signals of one long length (solved together as a group) mixed
+    with short ones, in interleaved order."""
+    sizes = [1 << 15, 1 << 11, 1 << 16, 1 << 15, 1 << 13, 1 << 16, 1 << 15, 1 << 10]
+    probs = mixed(d, sizes, 60 + d)
+    T = 20
+    got = run_batch(probs, d, T)
+    ref = batched.ista_batched(probs, T)
+    for i, (a, b) in enumerate(zip(got, ref)):
+        assert rel(a, b) <= IT_TOL, (i, sizes[i], rel(a, b))
+
+
+def test_batched_groups_repeat_and_reorder():
+    """A grouped batch twice gives identical results; the same signals in
+    another order (other group descriptors) give the same per-signal x."""
+    d = 4
+    sizes = [1 << 15, 1 << 12, 1 << 15, 1 << 17]
+    probs = mixed(d, sizes, 21)
+    a = run_batch(probs, d, 15)
+    b = run_batch(probs, d, 15)
+    assert all(np.array_equal(p, q) for p, q in zip(a, b))
+    perm = [3, 2, 1, 0]
+    c = run_batch([probs[i] for i in perm], d, 15)
+    for k, i in enumerate(perm):
+        assert np.array_equal(c[k], a[i])
