@@ -257,4 +257,82 @@ __device__ __forceinline__ void lds_fft(float2* __restrict__ buf,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Transforms whose first and last stages run in registers.  A caller that
+// already holds, for butterfly j < L/8 of sequence b, the eight elements
+// j + r*L/8 (r < 8) takes the first radix-8 stage (span 1) with
+// reg_stage_first, which leaves its outputs in LDS; lds_fft_mid runs the
+// stages between spans 8 and L/8 through LDS; reg_stage_last loads the last
+// radix-8 stage's inputs (span L/8, again the elements j + r*L/8 of each
+// butterfly) and leaves its outputs in registers, in natural order at the
+// same positions j + r*L/8.  This saves the LDS round trip at each end of
+// the transform, so a load from global memory, a pointwise step between two
+// transforms, or a store to global memory works on registers.  L >= 64.
+// Callers barrier after reg_stage_first's stores and before anything
+// overwrites the LDS that reg_stage_last reads.
+template <int L, int B, bool INV, bool ILV, int LD>
+__device__ __forceinline__ void reg_stage_first(float2* __restrict__ buf, float2 (&v)[8], unsigned b,
+                                                unsigned j) {
+  static_assert(L >= 64, "");
+  dft8<INV>(v);
+  // positions j*8 + r: one base plus constant offsets (r < 8 never crosses
+  // a 32-slot pad block because j*8 is a multiple of 8)
+  constexpr bool PADR = CS_ROW_PAD && !ILV && (B == 1 || LD % 32 == 0);
+  if constexpr (ILV) {
+    const unsigned base = (j * 8) * B + b;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) buf[lp(base + r * B)] = v[r];
+  } else if constexpr (PADR) {
+    const unsigned base = b * prc(LD) + lpr(j * 8);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) buf[base + r] = v[r];
+  } else {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) buf[lds_addr<ILV, B, LD>(b, j * 8 + r)] = v[r];
+  }
+}
+
+template <int L, int B, bool INV, bool ILV, int LD>
+__device__ __forceinline__ void reg_stage_last(const float2* __restrict__ buf, const float2* __restrict__ tw,
+                                               float2 (&v)[8], unsigned b, unsigned j) {
+  static_assert(L >= 64, "");
+  constexpr unsigned Q = L / 8;
+  constexpr bool PADR = CS_ROW_PAD && !ILV && (B == 1 || LD % 32 == 0) && Q % 32 == 0;
+  if constexpr (ILV) {
+    const unsigned base = j * B + b;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = buf[lp(base + r * Q * B)];
+  } else if constexpr (PADR) {
+    const unsigned base = b * prc(LD) + lpr(j);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = buf[base + prc(r * Q)];
+  } else {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = buf[lds_addr<ILV, B, LD>(b, j + r * Q)];
+  }
+  // twiddles W_L^{r j}: W^j and W^{4j} from the table, the rest by products
+  float2 w[8];
+  w[1] = tw[j];
+  w[2] = cmul(w[1], w[1]);
+  w[3] = cmul(w[2], w[1]);
+  w[4] = tw[4 * j];
+  w[5] = cmul(w[4], w[1]);
+  w[6] = cmul(w[4], w[2]);
+  w[7] = cmul(w[4], w[3]);
+#pragma unroll
+  for (int r = 1; r < 8; ++r) v[r] = INV ? cmulc(v[r], w[r]) : cmul(v[r], w[r]);
+  dft8<INV>(v);
+}
+
+template <int L, int B, int T, bool INV, bool ILV, int LD, int NS = 8>
+__device__ __forceinline__ void lds_fft_mid(float2* __restrict__ buf, const float2* __restrict__ tw,
+                                            unsigned tid) {
+  if constexpr (NS < L / 8) {
+    constexpr int p = ilog2c(L / (8 * NS));
+    constexpr int R = (p % 3 == 0) ? 8 : ((p % 3 == 2) ? 4 : (p == 1 ? 2 : 4));
+    stockham_stage<L, B, T, INV, ILV, LD, NS, R>(buf, tw, tid);
+    lds_fft_mid<L, B, T, INV, ILV, LD, NS * R>(buf, tw, tid);
+  }
+}
+
 }  // namespace cs

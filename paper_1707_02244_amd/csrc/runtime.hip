@@ -444,7 +444,10 @@ struct BatchState {
 
 // Signals from this length on are solved per length group (see
 // cs_ista_solve_batched).
-constexpr int64_t kGroupMinN = int64_t(1) << 15;
+#ifndef CS_GROUP_MIN_LOGN
+#define CS_GROUP_MIN_LOGN 15
+#endif
+constexpr int64_t kGroupMinN = int64_t(1) << CS_GROUP_MIN_LOGN;
 constexpr size_t kGroupChunkBytes = size_t(1) << 31;
 
 // Copy a length group's inputs into contiguous per-group arrays (grid y =

@@ -32,11 +32,36 @@
 #pragma once
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace cs {
 
 constexpr int kPThreads = 512;
+
+// Register-stage path (first and last radix-8 stage of every transform in
+// registers) for the larger sizes; CS_REG_MIN_N1 is the smallest N1 that
+// takes it (below it, too few threads would hold butterflies).
+#ifndef CS_REG_STAGES
+#define CS_REG_STAGES 1
+#endif
+#ifndef CS_REG_MIN_N1
+#define CS_REG_MIN_N1 512
+#endif
+
+// Pins a value to registers (an empty asm that claims to modify it), so a
+// select between two such values stays a select of registers.
+__device__ __forceinline__ void opaque(float2& v) { asm("" : "+v"(v.x), "+v"(v.y)); }
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
 constexpr unsigned kSpinLimit = 1u << 20;   // polls (~40 ms); a real wait is ~100 us
 
 struct SolveArgs {
@@ -77,6 +102,101 @@ __device__ __forceinline__ float2 ld_coh(const float2* p) {
 __device__ __forceinline__ void st_coh(float2* p, float2 v) {
   __hip_atomic_store(reinterpret_cast<uint64_t*>(p), __builtin_bit_cast(uint64_t, v), __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// 16-byte forms of ld_coh / st_coh (two adjacent float2) for the register-
+// stage path: raw buffer accesses with the same device-coherence cache bit
+// (sc1) that the relaxed agent-scope atomics above carry.  The buffer
+// resource covers exactly the spectrum buffer, so an offset outside it reads
+// zeros and drops the store instead of touching other memory.
+typedef unsigned cs_u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kCohAux = 16;                  // cache policy: sc1
+constexpr int kBufWord3 = 0x00020000;        // raw 32-bit buffer (gfx9 family)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t y_rsrc(float2* Y, unsigned n_elems) {
+  return __builtin_amdgcn_make_buffer_rsrc(Y, 0, (int)(n_elems * 8u), kBufWord3);
+}
+__device__ __forceinline__ void ld_coh_pair(__amdgpu_buffer_rsrc_t rs, unsigned elem, float2& lo, float2& hi) {
+  const cs_u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, elem * 8u, 0, kCohAux);
+  lo = c2(__uint_as_float(v.x), __uint_as_float(v.y));
+  hi = c2(__uint_as_float(v.z), __uint_as_float(v.w));
+}
+__device__ __forceinline__ void st_coh_pair(__amdgpu_buffer_rsrc_t rs, unsigned elem, float2 lo, float2 hi) {
+  // the values are pinned to registers first: otherwise the compiler may
+  // read the caller's array element and its neighbour as one 16-byte load,
+  // and an array read that way cannot stay in registers
+  asm("" : "+v"(lo.x), "+v"(lo.y), "+v"(hi.x), "+v"(hi.y));
+  const cs_u32x4 v = {__float_as_uint(lo.x), __float_as_uint(lo.y), __float_as_uint(hi.x),
+                      __float_as_uint(hi.y)};
+  __builtin_amdgcn_raw_buffer_store_b128(v, rs, elem * 8u, 0, kCohAux);
+}
+
+// One alias class of the row pass on registers (the same arithmetic as the
+// LDS form in k_solve).  The class's row-a values at p_l = k2 + l*M sit at
+// indices RHO + l*(8/D2) of A; their mirrors (row b at N2-1-p_l, or at
+// (N2-p_l) mod N2 in row 0) at indices 7-RHO-l*(8/D2) of Bv (MK = 0) or
+// (8-RHO-l*(8/D2)) mod 8 (MK = 1).  A and Bv may be the same array: every
+// input is read before any output is written.  WB = false for the classes
+// that are their own mirror (row 0, k2 = 0 and M/2).
+template <int D2, int M, int RHO, int MK, bool WB, int ALG, typename Args>
+__device__ __forceinline__ void class_step(float2 (&A)[8], float2 (&Bv)[8], const float2 (&gca)[D2],
+                                           const float2 (&gcb)[D2], float2 gy, unsigned k2, float2 wk1,
+                                           const float2* __restrict__ tp, const Args& a) {
+  constexpr int RM = 8 / D2;
+  float2 Xa[D2], Xb[D2], gw[D2];
+#pragma unroll
+  for (int l = 0; l < D2; ++l) {
+    const int ia = RHO + l * RM;
+    const int ib = MK == 0 ? 7 - RHO - l * RM : (8 - RHO - l * RM) & 7;
+    gw[l] = cmul(wk1, tp[k2 + l * M]);
+    const float2 za = A[ia];
+    const float2 zbc = cconj(Bv[ib]);
+    const float2 P = cscale(cadd(za, zbc), 0.5f);
+    const float2 Q = cscale(cmulmi(csub(za, zbc)), 0.5f);
+    const float2 wq = cmul(gw[l], Q);
+    Xa[l] = cadd(P, wq);
+    Xb[l] = cconj(csub(P, wq));
+  }
+  float2 Va[D2], Vb[D2];
+  if constexpr (ALG == 0) {
+    float2 s1 = c2(0.f, 0.f), s2 = c2(0.f, 0.f);
+#pragma unroll
+    for (int l = 0; l < D2; ++l) { s1 = cadd(s1, cmul(gca[l], Xa[l])); s2 = cadd(s2, cmul(gcb[l], Xb[l])); }
+    const float2 S = cscale(cadd(s1, cconj(s2)), a.inv_d);
+    const float2 E = cscale(csub(gy, S), a.tau);
+    const float2 Ec = cconj(E);
+#pragma unroll
+    for (int l = 0; l < D2; ++l) {
+      Va[l] = cconjmul(gca[l], E);
+      Vb[l] = cconjmul(gcb[l], Ec);
+    }
+  } else {
+    float2 r1 = c2(0.f, 0.f), r2 = c2(0.f, 0.f);
+    float den = a.d_rho;
+#pragma unroll
+    for (int l = 0; l < D2; ++l) {
+      r1 = cadd(r1, cmul(gca[l], Xa[l]));
+      r2 = cadd(r2, cmul(gcb[l], Xb[l]));
+      den += cabs2(gca[l]) + cabs2(gcb[l]);
+    }
+    const float2 S = cscale(cadd(r1, cconj(r2)), a.inv_d);
+    const float2 E = cscale(csub(gy, S), 1.0f / (den * a.inv_d));
+    const float2 Ec = cconj(E);
+#pragma unroll
+    for (int l = 0; l < D2; ++l) {
+      Va[l] = cadd(Xa[l], cconjmul(gca[l], E));
+      Vb[l] = cadd(Xb[l], cconjmul(gcb[l], Ec));
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < D2; ++l) {
+    const int ia = RHO + l * RM;
+    const int ib = MK == 0 ? 7 - RHO - l * RM : (8 - RHO - l * RM) & 7;
+    const float2 vbc = cconj(Vb[l]);
+    const float2 E_ = cscale(cadd(Va[l], vbc), a.inv_n);
+    const float2 O_ = cscale(cmulc(csub(Va[l], vbc), gw[l]), a.inv_n);
+    A[ia] = cadd(E_, cmuli(O_));
+    if constexpr (WB) Bv[ib] = cconj(csub(E_, cmuli(O_)));
+  }
 }
 
 // Grid-wide barrier.  Arrivals are spread over NC counters, each on its own
@@ -147,6 +267,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
   constexpr bool FB = NEB % T == 0;
   constexpr int M = N2 / D2;                 // alias classes per row (m / N1)
   constexpr int GPT = (AI * M + 1 + T - 1) / T;
+  constexpr bool REG = CS_REG_STAGES && N1 >= CS_REG_MIN_N1 && N1 >= 64 && N2 >= 64;
   __shared__ float2 lds[lds_padded(NL)];
   __shared__ float2 t1[N1];
   __shared__ float2 t2[N2];
@@ -165,6 +286,361 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
   for (int i = tid; i < N2; i += T) tp[i] = a.twp[i];
   for (int i = tid; i < (1 << LOB); i += T) tlo[i] = a.twlo[i];
   for (int i = tid; i < (N >> LOB); i += T) thi[i] = a.twhi[i];
+  if constexpr (REG) {
+    // ---- register-stage path ------------------------------------------------
+    // Row pass: thread (pair rpi, butterfly rt) loads the two rows of its
+    // pair at positions rt + r*Q with 16-byte accesses and takes the first
+    // forward stage in registers.  The last forward stage is taken in the
+    // mirror mapping (row a at jA, row b at jB = its mirror butterfly), so
+    // every alias class a thread updates has both of its sides in that
+    // thread's registers; the first inverse stage follows in registers, and
+    // the last inverse stage returns to the load mapping for the store.
+    // Column pass: thread (column cc, pair cu) holds butterflies cjA and cjB
+    // whose rows k1 and N1 - k1 share the 16-byte Y entries of a row pair;
+    // the threshold epilogue runs on registers between the last inverse and
+    // the first forward stage.
+    constexpr unsigned Q = N2 / 8;            // row butterflies per row
+    constexpr unsigned QC = N1 / 8;           // column butterflies per column
+    constexpr int RM = 8 / D2;                // classes per row butterfly
+    constexpr int NK = RM + 1;                // class slots (row 0 has one extra)
+    static_assert(AI * Q <= (unsigned)T && CB * QC / 2 <= (unsigned)T, "too few threads");
+    static_assert(M % Q == 0 && Q % 2 == 0 && QC % 2 == 0, "");
+    const __amdgpu_buffer_rsrc_t rs = y_rsrc(a.Y, (unsigned)N);
+
+    // row-pass roles: cat 0 = row pair {w, N1-w}; for pair 0 (rows 0 and
+    // N1/2, each its own mirror): cat 2 = row 0 butterflies {0, Q/2}, cat 1
+    // = row 0 butterflies {t, Q-t}, cat 3 = row N1/2 butterflies {u, Q-1-u}
+    const bool ract = tid < AI * Q;
+    unsigned rpi = tid / Q, rt = tid % Q;
+    unsigned wp = g + rpi * G;
+    int cat = -1;
+    unsigned jA = 0, jB = 0, sA = 0, sB = 0, rowA = 0, rowB = 0;
+    if (ract) {
+      if (wp == 0) {
+        if (rt < Q / 2) {
+          cat = rt ? 1 : 2;
+          jA = rt; jB = rt ? Q - rt : Q / 2; sA = sB = 2 * rpi; rowA = rowB = 0;
+        } else {
+          cat = 3;
+          jA = rt - Q / 2; jB = Q - 1 - jA; sA = sB = 2 * rpi + 1; rowA = rowB = N1 / 2;
+        }
+      } else {
+        cat = 0;
+        jA = rt; jB = Q - 1 - rt; sA = 2 * rpi; sB = 2 * rpi + 1; rowA = wp; rowB = N1 - wp;
+      }
+    }
+    // class operands of this thread's class slot k (c_hat at both sides,
+    // y_hat); with CS_REG_HOIST they are loaded once per solve into
+    // registers, otherwise before each use
+    float2 wk1 = c2(1.f, 0.f);
+    if (ract) wk1 = a.twk1[rowA];
+    auto slot_k2 = [&](int k, bool& valid, int& mode) __attribute__((always_inline)) -> unsigned {
+      unsigned k2 = 0;
+      valid = false;
+      mode = 0;
+      if (cat == 0) {
+        valid = k < RM; k2 = jA + k * Q;
+      } else if (cat == 2) {
+        valid = true; mode = 1;
+        if (RM >= 2) k2 = (k <= RM / 2) ? k * Q : Q / 2 + (k - RM / 2 - 1) * Q;
+        else k2 = (k == 0) ? 0 : Q / 2;
+      } else if (cat > 0) {
+        valid = k < RM; mode = (cat == 1) ? 1 : 2;
+        if (RM >= 2) k2 = (k < RM / 2) ? jA + k * Q : jB + (k - RM / 2) * Q;
+        else k2 = jA;
+      }
+      return valid ? k2 : 0;
+    };
+    auto load_ops = [&](int k, float2 (&gca)[D2], float2 (&gcb)[D2], float2& gy, unsigned& k2) __attribute__((always_inline)) {
+      bool valid;
+      int mode;
+      k2 = slot_k2(k, valid, mode);
+      gy = c2(0.f, 0.f);
+#pragma unroll
+      for (int l = 0; l < D2; ++l) { gca[l] = c2(0.f, 0.f); gcb[l] = c2(0.f, 0.f); }
+      if (valid) {
+#pragma unroll
+        for (int l = 0; l < D2; ++l) {
+          const unsigned pp = k2 + l * M;
+          const unsigned qq = (mode == 1) ? ((N2 - pp) & (N2 - 1)) : (N2 - 1 - pp);
+          gca[l] = a.chat[rowA * N2 + pp];
+          gcb[l] = (mode == 1 && pp == 0) ? a.chat[N] : a.chat[rowB * N2 + qq];
+        }
+        gy = a.yhat[rowA * N2 + k2];
+      }
+    };
+#ifndef CS_REG_HOIST
+#define CS_REG_HOIST 1
+#endif
+    float2 rca[CS_REG_HOIST ? NK : 1][D2], rcb[CS_REG_HOIST ? NK : 1][D2], ryv[CS_REG_HOIST ? NK : 1];
+    unsigned rk2[CS_REG_HOIST ? NK : 1];
+    if constexpr (CS_REG_HOIST) {
+      static_for<0, NK>([&](auto K) __attribute__((always_inline)) {
+        constexpr int k = decltype(K)::value;
+        load_ops(k, rca[k], rcb[k], ryv[k], rk2[k]);
+      });
+    }
+    // class step for slot KS with mapping (RHO, MK, WB) on arrays (X, Y)
+    auto cstep = [&](auto KS, auto RH, auto MKc, auto WBc, float2 (&X)[8], float2 (&Yv)[8]) __attribute__((always_inline)) {
+      constexpr int ks = decltype(KS)::value;
+      if constexpr (CS_REG_HOIST) {
+        class_step<D2, M, decltype(RH)::value, decltype(MKc)::value, decltype(WBc)::value, ALG>(
+            X, Yv, rca[ks], rcb[ks], ryv[ks], rk2[ks], wk1, tp, a);
+      } else {
+        float2 gca[D2], gcb[D2], gy;
+        unsigned k2;
+        load_ops(ks, gca, gcb, gy, k2);
+        class_step<D2, M, decltype(RH)::value, decltype(MKc)::value, decltype(WBc)::value, ALG>(
+            X, Yv, gca, gcb, gy, k2, wk1, tp, a);
+      }
+    };
+    auto row_elem = [&](unsigned r) __attribute__((always_inline)) -> unsigned { return (wp * N2 + rt + r * Q) * 2; };
+
+    // column-pass roles
+    const bool cact = tid < CB * QC / 2;
+    unsigned cc = tid % CB, cu = tid / CB;
+    unsigned cjA = cu, cjB = cu ? QC - cu : QC / 2;
+    unsigned j2c = j2_0 + cc;
+    auto twc = [&](unsigned k1) __attribute__((always_inline)) -> float2 {   // W_N^{(j2 * k1) mod N}
+      const unsigned ex = (j2c * k1) & (N - 1);
+      return cmul(tlo[ex & ((1u << LOB) - 1)], thi[ex >> LOB]);
+    };
+    auto pair_elem = [&](unsigned w) __attribute__((always_inline)) -> unsigned { return (w * N2 + j2c) * 2; };
+    // four-step twiddles of butterfly j's rows j + r*QC:
+    // W_N^{j2 (j + r QC)} = W_N^{j2 j} * w^r with w = W_N^{j2 QC}; w^r from
+    // w and w^4 by products (at most two), as in the FFT stages
+    struct ColTw { float2 bA, bB, w1, w2, w3, w4; };
+    auto col_tw = [&]() __attribute__((always_inline)) -> ColTw {
+      ColTw c;
+      c.bA = twc(cjA);
+      c.bB = twc(cjB);
+      c.w1 = twc(QC);
+      c.w4 = twc(4 * QC);
+      c.w2 = cmul(c.w1, c.w1);
+      c.w3 = cmul(c.w2, c.w1);
+      return c;
+    };
+    auto wpow = [&](const ColTw& c, int r) __attribute__((always_inline)) -> float2 {
+      const float2 lo = (r & 3) == 1 ? c.w1 : ((r & 3) == 2 ? c.w2 : c.w3);
+      if (r == 0) return c2(1.f, 0.f);
+      if (r == 4) return c.w4;
+      return r < 4 ? lo : cmul(c.w4, lo);
+    };
+    // Y entries of pairs cjA + r*QC and cjB + r*QC (r < 4) hold rows
+    // k1 = cjA + r*QC, cjB + r*QC (side 0) and N1 - k1 (side 1); for cu > 0
+    // the latter are butterfly cjB / cjA at 7 - r, for cu = 0 (butterflies 0
+    // and QC/2, each its own mirror) they are the same butterfly at
+    // (8 - r) mod 8 (r = 0: row N1/2, index 4) and 7 - r.
+    auto col_load = [&](float2 (&A)[8], float2 (&B)[8]) __attribute__((always_inline)) {
+      float2 lo[4], hi[4], lo2[4], hi2[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        ld_coh_pair(rs, pair_elem(cjA + r * QC), lo[r], hi[r]);
+        ld_coh_pair(rs, pair_elem(cjB + r * QC), lo2[r], hi2[r]);
+      }
+      // every element is written at a fixed index with a value select of
+      // opaque register values: stores at different indices in two branches,
+      // or a select of two array loads, would become an access through a
+      // selected address, which moves the arrays to scratch memory
+      const ColTw ct = col_tw();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float2 h1 = hi[r], h2 = hi2[r], h3 = hi[(r + 1) & 3];
+        opaque(h1); opaque(h2); opaque(h3);
+        const float2 wl = wpow(ct, r), wh = wpow(ct, 7 - r);
+        A[r] = cmulc(lo[r], cmul(ct.bA, wl));
+        B[r] = cmulc(lo2[r], cmul(ct.bB, wl));
+        A[7 - r] = cmulc(cu ? h2 : h3, cmul(ct.bA, wh));
+        B[7 - r] = cmulc(cu ? h1 : h2, cmul(ct.bB, wh));
+      }
+    };
+    auto col_store = [&](float2 (&A)[8], float2 (&B)[8]) __attribute__((always_inline)) {
+      const ColTw ct = col_tw();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const float2 wr = wpow(ct, r);
+        A[r] = cmul(A[r], cmul(ct.bA, wr));
+        B[r] = cmul(B[r], cmul(ct.bB, wr));
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float2 b7 = B[7 - r], a7 = A[7 - r], a8 = A[r == 0 ? 4 : 8 - r];
+        opaque(b7); opaque(a7); opaque(a8);
+        st_coh_pair(rs, pair_elem(cjA + r * QC), A[r], cu ? b7 : a8);
+        st_coh_pair(rs, pair_elem(cjB + r * QC), B[r], cu ? a7 : b7);
+      }
+    };
+    // forward column transform of (A, B) (time domain) and store to Y
+    auto col_forward = [&](float2 (&A)[8], float2 (&B)[8]) __attribute__((always_inline)) {
+      if (cact) {
+        reg_stage_first<N1, CB, false, true, N1>(lds, A, cc, cjA);
+        reg_stage_first<N1, CB, false, true, N1>(lds, B, cc, cjB);
+      }
+      __syncthreads();
+      lds_fft_mid<N1, CB, T, false, true, N1>(lds, t1, tid);
+      if (cact) {
+        reg_stage_last<N1, CB, false, true, N1>(lds, t1, A, cc, cjA);
+        reg_stage_last<N1, CB, false, true, N1>(lds, t1, B, cc, cjB);
+        col_store(A, B);
+      }
+    };
+    auto sidx = [&](unsigned j, unsigned r) __attribute__((always_inline)) -> unsigned { return (j + r * QC) * N2 + j2c; };
+
+    // time-domain state of butterflies cjA, cjB (ISTA: x; ADMM: u)
+    float2 stA[8], stB[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) { stA[r] = c2(0.f, 0.f); stB[r] = c2(0.f, 0.f); }
+    unsigned nbar = 0;
+    constexpr int NC = G < kBarCounters ? G : kBarCounters;
+    constexpr unsigned PER_C = G / NC;
+
+    if (ALG == 1 && a.warm) {
+      const float2* z2 = reinterpret_cast<const float2*>(a.z);
+      const float2* u2 = reinterpret_cast<const float2*>(a.u);
+      float2 A[8], B[8];
+      if (cact) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          stA[r] = u2[sidx(cjA, r)];
+          stB[r] = u2[sidx(cjB, r)];
+          A[r] = csub(z2[sidx(cjA, r)], stA[r]);
+          B[r] = csub(z2[sidx(cjB, r)], stB[r]);
+        }
+      }
+      col_forward(A, B);
+      grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err);
+    }
+    __syncthreads();
+
+    for (int t = 1; t <= a.iters; ++t) {
+      // recompute per-thread indices inside the iteration (hoisting them out
+      // of the loop keeps dozens of addresses live and forces spills)
+      asm volatile("" : "+v"(rpi), "+v"(rt), "+v"(wp), "+v"(jA), "+v"(jB), "+v"(sA), "+v"(sB));
+      asm volatile("" : "+v"(cc), "+v"(cu), "+v"(cjA), "+v"(cjB), "+v"(j2c));
+      // ---- row pass ----------------------------------------------------------
+      float2 va[8], vb[8];
+      const bool zero_in = (t == 1) && !(ALG == 1 && a.warm);
+      if (ract) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          if (zero_in) { va[r] = c2(0.f, 0.f); vb[r] = c2(0.f, 0.f); }
+          else ld_coh_pair(rs, row_elem(r), va[r], vb[r]);
+        }
+        reg_stage_first<N2, RA, false, false, LDA>(lds, va, 2 * rpi, rt);
+        reg_stage_first<N2, RA, false, false, LDA>(lds, vb, 2 * rpi + 1, rt);
+      }
+      __syncthreads();
+      lds_fft_mid<N2, RA, T, false, false, LDA>(lds, t2, tid);
+      if (ract) {
+        reg_stage_last<N2, RA, false, false, LDA>(lds, t2, va, sA, jA);
+        reg_stage_last<N2, RA, false, false, LDA>(lds, t2, vb, sB, jB);
+      }
+      __syncthreads();
+      {
+        using std::integral_constant;
+        using I0 = integral_constant<int, 0>;
+        using I1 = integral_constant<int, 1>;
+        using BT = std::true_type;
+        using BF = std::false_type;
+        if (cat == 0) {
+          static_for<0, RM>([&](auto K) __attribute__((always_inline)) { cstep(K, K, I0{}, BT{}, va, vb); });
+        } else if (cat == 1 || cat == 3) {
+          if constexpr (RM >= 2) {
+            static_for<0, RM / 2>([&](auto K) __attribute__((always_inline)) {
+              cstep(K, K, I0{}, BT{}, va, vb);
+              cstep(integral_constant<int, RM / 2 + decltype(K)::value>{}, K, I0{}, BT{}, vb, va);
+            });
+          } else {
+            cstep(I0{}, I0{}, I0{}, BT{}, va, vb);
+          }
+        } else if (cat == 2) {
+          if constexpr (RM >= 2) {
+            static_for<0, RM / 2 + 1>([&](auto K) __attribute__((always_inline)) {
+              constexpr int k = decltype(K)::value;
+              cstep(K, K, I1{}, std::bool_constant<(k != 0 && k != RM / 2)>{}, va, va);
+            });
+            static_for<0, RM / 2>([&](auto K) __attribute__((always_inline)) {
+              cstep(integral_constant<int, RM / 2 + 1 + decltype(K)::value>{}, K, I0{}, BT{}, vb, vb);
+            });
+          } else {
+            cstep(I0{}, I0{}, I1{}, BF{}, va, va);
+            cstep(I1{}, I0{}, I0{}, BF{}, vb, vb);
+          }
+        }
+      }
+      if (ract) {
+        reg_stage_first<N2, RA, true, false, LDA>(lds, va, sA, jA);
+        reg_stage_first<N2, RA, true, false, LDA>(lds, vb, sB, jB);
+      }
+      __syncthreads();
+      lds_fft_mid<N2, RA, T, true, false, LDA>(lds, t2, tid);
+      if (ract) {
+        reg_stage_last<N2, RA, true, false, LDA>(lds, t2, va, 2 * rpi, rt);
+        reg_stage_last<N2, RA, true, false, LDA>(lds, t2, vb, 2 * rpi + 1, rt);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) st_coh_pair(rs, row_elem(r), va[r], vb[r]);
+      }
+      grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err);
+
+      // ---- column pass -------------------------------------------------------
+      float2 A[8], B[8];
+      if (cact) {
+        col_load(A, B);
+        reg_stage_first<N1, CB, true, true, N1>(lds, A, cc, cjA);
+        reg_stage_first<N1, CB, true, true, N1>(lds, B, cc, cjB);
+      }
+      __syncthreads();
+      lds_fft_mid<N1, CB, T, true, true, N1>(lds, t1, tid);
+      if (cact) {
+        reg_stage_last<N1, CB, true, true, N1>(lds, t1, A, cc, cjA);
+        reg_stage_last<N1, CB, true, true, N1>(lds, t1, B, cc, cjB);
+      }
+      __syncthreads();
+      const bool last = (t == a.iters);
+      const float thr = a.thr;
+      if (cact) {
+        auto epi = [&](float2& v, float2& s, unsigned j, unsigned r) __attribute__((always_inline)) {
+          if constexpr (ALG == 0) {
+            const float2 w = cadd(s, v);
+            const float2 xv = c2(soft(w.x, thr), soft(w.y, thr));
+            s = xv;
+            v = xv;
+          } else {
+            const float2 xv = v;
+            const float2 xu = cadd(xv, s);
+            const float2 zv = c2(soft(xu.x, thr), soft(xu.y, thr));
+            const float2 u1 = csub(xu, zv);
+            s = u1;
+            if (last) {
+              reinterpret_cast<float2*>(a.x)[sidx(j, r)] = xv;
+              reinterpret_cast<float2*>(a.z)[sidx(j, r)] = zv;
+            } else {
+              v = csub(zv, u1);
+            }
+          }
+        };
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          epi(A[r], stA[r], cjA, r);
+          epi(B[r], stB[r], cjB, r);
+        }
+      }
+      if (!last) {
+        col_forward(A, B);
+        grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err);
+      }
+    }
+
+    // ---- outputs -----------------------------------------------------------
+    float2* out = reinterpret_cast<float2*>(ALG == 0 ? a.x : a.u);
+    if ((ALG == 0 || a.iters > 0) && cact) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        out[sidx(cjA, r)] = stA[r];
+        out[sidx(cjB, r)] = stB[r];
+      }
+    }
+  } else {
   // W_N^{(j2 * k1) mod N} for column-pass element e
   auto twb = [&](unsigned e) -> float2 {
     const unsigned ex = ((j2_0 + (e % CB)) * (e / CB)) & (N - 1);
@@ -432,6 +908,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
       const unsigned e = tid + k * T;
       if (FB || e < NEB) out[col_index(e)] = st[k];
     }
+  }
   }
 }
 
