@@ -324,12 +324,17 @@ __device__ __forceinline__ void reg_stage_last(const float2* __restrict__ buf, c
   dft8<INV>(v);
 }
 
+#ifndef CS_MID_RADIX16
+#define CS_MID_RADIX16 1
+#endif
 template <int L, int B, int T, bool INV, bool ILV, int LD, int NS = 8>
 __device__ __forceinline__ void lds_fft_mid(float2* __restrict__ buf, const float2* __restrict__ tw,
                                             unsigned tid) {
   if constexpr (NS < L / 8) {
+    // radix 8 (radix 16 when exactly 16 remains: one LDS round trip instead
+    // of two), with one radix-4 or radix-2 stage for the remaining factor
     constexpr int p = ilog2c(L / (8 * NS));
-    constexpr int R = (p % 3 == 0) ? 8 : ((p % 3 == 2) ? 4 : (p == 1 ? 2 : 4));
+    constexpr int R = (p == 4 && CS_MID_RADIX16) ? 16 : (p % 3 == 0) ? 8 : ((p % 3 == 2) ? 4 : (p == 1 ? 2 : 4));
     stockham_stage<L, B, T, INV, ILV, LD, NS, R>(buf, tw, tid);
     lds_fft_mid<L, B, T, INV, ILV, LD, NS * R>(buf, tw, tid);
   }

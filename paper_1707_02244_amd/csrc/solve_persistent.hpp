@@ -384,8 +384,11 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
     auto cstep = [&](auto KS, auto RH, auto MKc, auto WBc, float2 (&X)[8], float2 (&Yv)[8]) __attribute__((always_inline)) {
       constexpr int ks = decltype(KS)::value;
       if constexpr (CS_REG_HOIST) {
+        bool valid;
+        int mode;
+        const unsigned k2 = slot_k2(ks, valid, mode);   // recomputed: cheaper than a held register
         class_step<D2, M, decltype(RH)::value, decltype(MKc)::value, decltype(WBc)::value, ALG>(
-            X, Yv, rca[ks], rcb[ks], ryv[ks], rk2[ks], wk1, tp, a);
+            X, Yv, rca[ks], rcb[ks], ryv[ks], k2, wk1, tp, a);
       } else {
         float2 gca[D2], gcb[D2], gy;
         unsigned k2;
