@@ -186,6 +186,19 @@ def main():
         out["kernels"] = kern
         out["bytes_model"] = ITER_BYTES_NOTE
         cs.check_device()
+        # context for the roofline: the compulsory-bytes rate (state in and
+        # out, c_hat, y_hat once per iteration: 13n ISTA, 13.5n ADMM) shows
+        # the schedule's overhead, and a plain copy kernel measured on this
+        # GPU gives the bandwidth a streaming kernel reaches here
+        copy_gbs = copy_bandwidth(torch, dev)
+        out["roofline_context"] = {
+            "compulsory_bytes_per_iteration": {"ista": 13 * n, "admm": 27 * n // 2},
+            "ista_compulsory_GBs": 13 * n * T_ista / (ista_ms / 1e3) / 1e9,
+            "admm_compulsory_GBs": 27 * n // 2 * T_admm / (admm_ms / 1e3) / 1e9,
+            "copy_kernel": "torch.neg over 1 GiB (reads 1 GiB, writes 1 GiB), HIP events, 5 launches",
+            "copy_GBs": copy_gbs,
+            "achieved_over_copy": ach / copy_gbs,
+        }
 
     if not args.no_batched:
         out["batched"] = bench_batched(cs, torch, dev, args.steps, args.warmup)
@@ -253,7 +266,26 @@ def bench_batched(cs, torch, dev, steps, warmup):
             "signals_per_s": len(sigs) / (ms / 1e3),
             "signal_iterations_per_s": len(sigs) * iters / (ms / 1e3),
             "model_GBs": bytes_it * iters / (ms / 1e3) / 1e9,
+            "compulsory_GBs": 13 * sum_n * iters / (ms / 1e3) / 1e9,
             "equiv_n2e22_it_s": sum_n * iters / (1 << 22) / (ms / 1e3)}
+
+
+def copy_bandwidth(torch, dev):
+    """GB/s of a plain elementwise copy-like kernel (read 1 GiB, write 1 GiB),
+    larger than the Infinity Cache so it streams from HBM."""
+    src = torch.ones(1 << 28, device=dev)
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        torch.neg(src, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 5 / 1e3
+    del src, dst
+    return 2 * 4 * (1 << 28) / sec / 1e9
 
 
 def bench_2d(cs, torch, dev, steps, warmup, with_oracle):
@@ -304,6 +336,7 @@ def bench_2d(cs, torch, dev, steps, warmup, with_oracle):
                        "+-1 sensing kernel, 2x2 decimation; ADMM rho=1, 200 it per solve",
            "ms_per_solve": ms, "iterations_per_s": T / (ms / 1e3),
            "bytes_per_iteration": it_bytes, "model_GBs": it_bytes * T / (ms / 1e3) / 1e9,
+           "compulsory_GBs": 27 * R * C // 2 * T / (ms / 1e3) / 1e9,
            "kernels": kern}
     if kern:
         dom = max(kern, key=lambda k: kern[k]["avg_us"])
