@@ -87,6 +87,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-2d", action="store_true")
     ap.add_argument("--no-unrolled", action="store_true")
+    ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain copy kernel (read and write this many MiB, 3 launches): the "
                          "known-size reference that scales profiler byte counters")
@@ -206,6 +207,8 @@ def main():
         out["deblur_2d"] = bench_2d(cs, torch, dev, args.steps, args.warmup, not args.no_cpu_baseline)
     if not args.no_unrolled:
         out["unrolled"] = bench_unrolled(cs, torch, dev, args.steps, args.warmup)
+    if not args.no_direct:
+        out["direct_baseline"] = bench_direct(cs, torch, dev, c, d, xs, y)
 
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib << 18, device=dev)
@@ -268,6 +271,45 @@ def bench_batched(cs, torch, dev, steps, warmup):
             "model_GBs": bytes_it * iters / (ms / 1e3) / 1e9,
             "compulsory_GBs": 13 * sum_n * iters / (ms / 1e3) / 1e9,
             "equiv_n2e22_it_s": sum_n * iters / (1 << 22) / (ms / 1e3)}
+
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X fp32 vector peak (counts packed FP32; these kernels are built without it)
+
+
+def bench_direct(cs, torch, dev, c, d, xs, y):
+    """The paper's direct formulation (one inner product over c per output,
+    O(n m) work) against the FFT operators at the headline shape
+    (n = 2^22, d = 4): ms per product and the ratio, HIP events."""
+    n = c.numel()
+    m = n // d
+
+    def ms(f, reps):
+        f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    yd = torch.empty(m, device=dev)
+    xd = torch.empty(n, device=dev)
+    fwd_ms = ms(lambda: cs.circ_apply_direct(c, d, xs, yd), 2)
+    adj_ms = ms(lambda: cs.circ_apply_T_direct(c, d, y, xd), 2)
+    fft_fwd_ms = ms(lambda: cs.circ_apply(c, d, xs, yd), 20)
+    fft_adj_ms = ms(lambda: cs.circ_apply_T(c, d, y, xd), 20)
+    flops = 2.0 * n * m
+    tf = flops / (fwd_ms / 1e3) / 1e12
+    return {"workload": "A x and A^T r at n=2^22, m=2^20 (d=4) with the headline's c, x and y",
+            "direct_fwd_ms": fwd_ms, "direct_adj_ms": adj_ms,
+            "fft_fwd_ms": fft_fwd_ms, "fft_adj_ms": fft_adj_ms,
+            "fwd_ratio": fwd_ms / fft_fwd_ms, "adj_ratio": adj_ms / fft_adj_ms,
+            "roofline": {"bound": "alu", "kernel": "direct", "achieved": tf,
+                         "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tf / FP32_VECTOR_PEAK_TFLOPS,
+                         "flops_per_launch": flops},
+            "adj_TFLOPs": flops / (adj_ms / 1e3) / 1e12}
 
 
 def copy_bandwidth(torch, dev):

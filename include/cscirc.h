@@ -57,6 +57,22 @@ cs_status cs_circ_apply(const float* c, int64_t n, int32_t d, const float* x, fl
 cs_status cs_circ_apply_T(const float* c, int64_t n, int32_t d, const float* r, float* x,
                           cs_stream stream);
 
+/* The same two products evaluated directly, without the FFT: every output
+ * is an inner product over the generator c, as in the paper's GPU kernels
+ * (Section 4: the CPISTA residual kernel takes a row of A times x, the
+ * thresholded-gradient kernel a row of A^T times r, reading only c):
+ *     y_i = sum_{j<n} c[(d i - j) mod n] x_j   (i < m),
+ *     x_j = sum_{i<m} c[(d i - j) mod n] r_i   (j < n).
+ * Arguments, layouts, ownership and errors as cs_circ_apply /
+ * cs_circ_apply_T (device pointers; c: n, x: n, y: m, r: m; no allocation).
+ * O(n m) work with FP32 accumulation in input order: a baseline that shows
+ * what the FFT formulation buys over direct inner products, not a solver
+ * path.  */
+cs_status cs_circ_apply_direct(const float* c, int64_t n, int32_t d, const float* x, float* y,
+                               cs_stream stream);
+cs_status cs_circ_apply_T_direct(const float* c, int64_t n, int32_t d, const float* r, float* x,
+                                 cs_stream stream);
+
 /* max_k |c_hat_k|^2 over the n-point DFT of c, written to out[0] (device).
  * It bounds ||A||_2^2 from above, so tau = 1/out is an admissible ISTA step
  * (Alg. 1 asks for tau in (0, ||A||_2^-2)).  */
@@ -194,7 +210,8 @@ cs_status cs_check_device(cs_stream stream);
  * hipEvents recorded on the caller's stream.  cs_timing_read waits for the
  * recorded launches of one kernel ("passA_ista", "passB_ista", "passA_admm",
  * "passB_admm", the persistent "solve_ista", "solve_admm", the batched
- * "batch_ista", or the 2-D "col2_ista", "row2_ista", "col2_admm",
+ * "batch_ista", the direct products "direct", "direct_T", or the 2-D
+ * "col2_ista", "row2_ista", "col2_admm",
  * "row2_admm"), returns their count and summed duration in milliseconds,
  * and forgets them.  Timing adds event records to the stream; leave it off
  * for production runs.  */

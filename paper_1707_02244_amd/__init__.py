@@ -4,6 +4,7 @@ The compute path is the HIP library libcscirc.so (C ABI in include/cscirc.h);
 this package only marshals torch tensors into it.
 """
 from ._lib import (CsError, LIB_PATH, EXPORTS, load, circ_apply, circ_apply_T,  # noqa: F401
+                   circ_apply_direct, circ_apply_T_direct,
                    circ_norm_bound, ista_solve, admm_solve, ista_solve_batched, batch_offsets,
                    unrolled_ckpt_bytes, unrolled_ista_fwd, unrolled_ista_bwd,
                    apply2, apply2_T, norm_bound2, ista_solve2, admm_solve2, timing_enable, timing_read, version,

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libcscirc.so")
 CS_OK, CS_EINVAL, CS_ENOMEM, CS_EHIP, CS_ENOTSUP = 0, -1, -2, -3, -4
 _NAMES = {CS_EINVAL: "CS_EINVAL", CS_ENOMEM: "CS_ENOMEM", CS_EHIP: "CS_EHIP", CS_ENOTSUP: "CS_ENOTSUP"}
 
-EXPORTS = ["cs_circ_apply", "cs_circ_apply_T", "cs_circ_norm_bound", "cs_ista_solve",
+EXPORTS = ["cs_circ_apply", "cs_circ_apply_T", "cs_circ_apply_direct", "cs_circ_apply_T_direct", "cs_circ_norm_bound", "cs_ista_solve",
            "cs_admm_solve", "cs_ista_solve_batched", "cs_unrolled_ckpt_bytes", "cs_unrolled_ista_fwd",
            "cs_unrolled_ista_bwd", "cs2_apply", "cs2_apply_T", "cs2_norm_bound", "cs2_ista_solve",
            "cs2_admm_solve", "cs_set_solver_path", "cs_check_device", "cs_timing_enable",
@@ -45,6 +45,8 @@ def load():
     sig = {
         "cs_circ_apply": [P, I64, I32, P, P, P],
         "cs_circ_apply_T": [P, I64, I32, P, P, P],
+        "cs_circ_apply_direct": [P, I64, I32, P, P, P],
+        "cs_circ_apply_T_direct": [P, I64, I32, P, P, P],
         "cs_circ_norm_bound": [P, I64, P, P],
         "cs_ista_solve": [P, I64, I32, P, F, F, I32, P, P, P],
         "cs_admm_solve": [P, I64, I32, P, F, F, I32, I32, P, P, P, P, P],
@@ -118,6 +120,27 @@ def circ_apply_T(c, d, r, x=None):
     if x is None:
         x = torch.empty(n, device=c.device, dtype=torch.float32)
     _check(load().cs_circ_apply_T(_ptr(c, "c"), n, d, _ptr(r, "r", n // d), _ptr(x, "x", n), _stream(c)))
+    return x
+
+
+def circ_apply_direct(c, d, x, y=None):
+    """y = P C x evaluated directly (no FFT): one inner product over c per
+    output, O(n m) work; a baseline beside circ_apply."""
+    import torch
+    n = c.numel()
+    if y is None:
+        y = torch.empty(n // d, device=c.device, dtype=torch.float32)
+    _check(load().cs_circ_apply_direct(_ptr(c, "c"), n, d, _ptr(x, "x", n), _ptr(y, "y", n // d), _stream(c)))
+    return y
+
+
+def circ_apply_T_direct(c, d, r, x=None):
+    """x = C^T P^T r evaluated directly (no FFT), O(n m) work."""
+    import torch
+    n = c.numel()
+    if x is None:
+        x = torch.empty(n, device=c.device, dtype=torch.float32)
+    _check(load().cs_circ_apply_T_direct(_ptr(c, "c"), n, d, _ptr(r, "r", n // d), _ptr(x, "x", n), _stream(c)))
     return x
 
 

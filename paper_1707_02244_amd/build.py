@@ -54,6 +54,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         units.append((os.path.join(CSRC, "inst2d_col.hip"), os.path.join(BUILD, "col2_%d.o" % L), ["-DCS_LEN=%d" % L]))
     for L in ROW2_LENGTHS:
         units.append((os.path.join(CSRC, "inst2d_row.hip"), os.path.join(BUILD, "row2_%d.o" % L), ["-DCS_LEN=%d" % L]))
+    units.append((os.path.join(CSRC, "inst_direct.hip"), os.path.join(BUILD, "direct.o"), []))
     units.append((os.path.join(CSRC, "runtime.hip"), os.path.join(BUILD, "runtime.o"), []))
     units.append((os.path.join(CSRC, "runtime2d.hip"), os.path.join(BUILD, "runtime2d.o"), []))
     units.sort(key=lambda u: ("solve" not in u[1] and "batch" not in u[1], -len(u[1])))

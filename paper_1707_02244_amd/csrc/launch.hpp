@@ -45,4 +45,9 @@ hipError_t launch2_col(int op, int grid, const Col2Args& a, hipStream_t s);
 template <int H>
 hipError_t launch2_row(int mode, int grid, const Row2Args& a, hipStream_t s);
 
+// direct (FFT-free) A x (transpose = 0) or A^T r (transpose = 1), d in
+// {2, 4, 8, 16} (inst_direct.hip)
+hipError_t launch_direct(int transpose, int d, const float* c, const float* in, float* out, long long n,
+                         hipStream_t s);
+
 }  // namespace cs

@@ -57,7 +57,7 @@ cs_status max_abs2(const float2* t, int count, float* out, hipStream_t s);
 // Timed launch kinds (names as reported by cs_timing_read).
 enum TimedKind {
   T_A_ISTA = 0, T_B_ISTA, T_A_ADMM, T_B_ADMM, T_S_ISTA, T_S_ADMM, T_BATCH,
-  T_C2_ISTA, T_R2_ISTA, T_C2_ADMM, T_R2_ADMM, T_COUNT
+  T_C2_ISTA, T_R2_ISTA, T_C2_ADMM, T_R2_ADMM, T_DIRECT, T_DIRECT_T, T_COUNT
 };
 bool timing_on();
 // Records the start (tok == -1 on entry) or the stop event of a launch.

@@ -140,7 +140,8 @@ std::vector<TimedLaunch> g_open;
 std::vector<hipEvent_t> g_event_pool;
 const char* kTimedNames[T_COUNT] = {"passA_ista", "passB_ista", "passA_admm", "passB_admm",
                                     "solve_ista", "solve_admm", "batch_ista",
-                                    "col2_ista", "row2_ista", "col2_admm", "row2_admm"};
+                                    "col2_ista", "row2_ista", "col2_admm", "row2_admm", "direct",
+                                    "direct_T"};
 
 hipEvent_t take_event() {
   if (!g_event_pool.empty()) {
@@ -1112,6 +1113,28 @@ cs_status cs_circ_apply_T(const float* c, int64_t n, int32_t d, const float* r, 
   b = argsB(*P);
   b.out0 = x;
   CS_LAUNCH(launchB(*P, B_OUT_ALL, b, s));
+  g_err.clear();
+  return CS_OK;
+}
+
+cs_status cs_circ_apply_direct(const float* c, int64_t n, int32_t d, const float* x, float* y,
+                               cs_stream stream) {
+  cs_status st = check_common(c, n, d);
+  if (st != CS_OK) return st;
+  if (!x || !y) return fail(CS_EINVAL, "x or y is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  CS_LAUNCH(timed(T_DIRECT, s, [&] { return launch_direct(0, d, c, x, y, n, s); }));
+  g_err.clear();
+  return CS_OK;
+}
+
+cs_status cs_circ_apply_T_direct(const float* c, int64_t n, int32_t d, const float* r, float* x,
+                                 cs_stream stream) {
+  cs_status st = check_common(c, n, d);
+  if (st != CS_OK) return st;
+  if (!r || !x) return fail(CS_EINVAL, "r or x is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  CS_LAUNCH(timed(T_DIRECT_T, s, [&] { return launch_direct(1, d, c, r, x, n, s); }));
   g_err.clear();
   return CS_OK;
 }
