@@ -482,3 +482,30 @@ def test_planted_mistakes_are_caught(case):
             check_dense_vs_fft(dense.dense_A, _MutAdjointConj, 64, 4)
         elif case == "decimate_offset":
             check_dense_vs_fft(dense.dense_A, _MutDecimateOffset, 64, 4)
+
+
+# ----------------------------------------------------------------------------
+# Compressed deblurring (Section 7): A = P C B with B the order-L box blur
+# ----------------------------------------------------------------------------
+def test_deblur_composite_generator_matches_dense_product():
+    """The circulant generated by composite_generator(c, L) equals the dense
+    product C B built from the definitions (brute force, n = 64)."""
+    from oracle import deblur
+    n, L = 64, 5
+    rng = np.random.default_rng(11)
+    c = rng.standard_normal(n)
+    C = deblur.dense_circulant(c)
+    B = deblur.dense_box_blur(n, L)
+    CB = C @ B
+    G = deblur.dense_circulant(deblur.composite_generator(c, L))
+    assert np.allclose(G, CB, atol=1e-13)
+    # B averages L consecutive samples starting at the output index
+    x = rng.standard_normal(n)
+    assert np.allclose(B @ x, [np.mean(x[(i + np.arange(L)) % n]) for i in range(n)])
+
+
+def test_deblur_field_shape():
+    import workloads
+    sig = workloads.deblur_field(side=64)
+    assert sig.n == 64 * 64 and sig.d == 2 and sig.k == int(0.1 * sig.n)
+    assert np.count_nonzero(sig.x_true) == sig.k and np.all(sig.x_true >= 0)

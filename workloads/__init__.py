@@ -151,3 +151,27 @@ def cfg5(seed_offset: int = 0, n: int = 1 << 16, d: int = 4, batch: int = 64, k:
 
 
 CFG5_PARAMS = dict(K=50, every=10, lam_frac=0.01)
+
+
+def deblur_field(seed_offset: int = 0, side: int = 1024, frac: float = 0.1):
+    """The deblurring shape of Section 7 on a synthetic field: a side x side
+    image vectorised (n = side^2), about frac * n nonzero pixels with
+    lognormal(0, 1) intensities at uniform positions (a star field standing
+    in for the telescope image, which is not available), a Gaussian
+    generator c ~ N(0, 1/m) with m = n/2 (d = 2).  The 1-D box blur of order
+    DEBLUR1D_PARAMS["L"] that the sensing operator composes with c is not
+    applied here.  Draw order: c, support, values."""
+    rng = np.random.default_rng(SEED_BASE + 6 + seed_offset)
+    n = side * side
+    d = 2
+    m = n // d
+    k = int(frac * n)
+    c = rng.standard_normal(n) / np.sqrt(m)
+    supp = rng.choice(n, k, replace=False)
+    vals = rng.lognormal(0.0, 1.0, k)
+    x = np.zeros(n)
+    x[supp] = vals
+    return Signal1D(n=n, d=d, k=k, c=_f32(c), x_true=_f32(x), support=np.sort(supp.astype(np.int64)))
+
+
+DEBLUR1D_PARAMS = dict(L=5, admm_iters=300, rho=1.0, lam=1e-2)
