@@ -103,8 +103,8 @@ def main():
     import workloads
 
     dev = torch.device("cuda:0")
-    sig = workloads.cfg2()
-    prm = workloads.CFG2_PARAMS
+    sig = workloads.large_signal()
+    prm = workloads.LARGE_PARAMS
     n, d = sig.n, sig.d
     c = torch.from_numpy(sig.c).to(dev)
     xs = torch.from_numpy(sig.x_true).to(dev)
@@ -233,8 +233,8 @@ def bench_batched(cs, torch, dev, steps, warmup):
     Inputs (y, tau, lam) computed with the library's operators."""
     import numpy as np
     import workloads
-    sigs = workloads.cfg4()
-    iters = workloads.CFG4_PARAMS["ista_iters"]
+    sigs = workloads.uneven_batch()
+    iters = workloads.UNEVEN_PARAMS["ista_iters"]
     d = 4
     ns = np.array([s.n for s in sigs], dtype=np.int64)
     c_cat = torch.from_numpy(np.concatenate([s.c for s in sigs])).to(dev)
@@ -249,7 +249,7 @@ def bench_batched(cs, torch, dev, steps, warmup):
         yi = y_cat[off_m[i]:off_m[i] + n // d]
         cs.circ_apply(ci, d, x_true[off_n[i]:off_n[i] + n], yi)
         tau[i] = 1.0 / cs.circ_norm_bound(ci)[0]
-        lam[i] = workloads.CFG4_PARAMS["lam_frac"] * cs.circ_apply_T(ci, d, yi).abs().max()
+        lam[i] = workloads.UNEVEN_PARAMS["lam_frac"] * cs.circ_apply_T(ci, d, yi).abs().max()
     x_cat = torch.empty_like(c_cat)
     run = lambda: cs.ista_solve_batched(ns, d, c_cat, y_cat, lam, tau, iters, x_cat)
     for _ in range(max(1, warmup)):
@@ -377,8 +377,8 @@ def bench_2d(cs, torch, dev, steps, warmup, with_oracle):
     ADMM rho = 1, 200 iterations per solve (setup of DFT2(s) DFT2(h) and
     DFT2(y) included in each solve).  y and lam from the library's operators."""
     import workloads
-    sc = workloads.cfg3()
-    prm = workloads.CFG3_PARAMS
+    sc = workloads.scene_2d()
+    prm = workloads.SCENE2D_PARAMS
     R, C = sc.n1, sc.n2
     s_ = torch.from_numpy(sc.s).to(dev)
     h_ = torch.from_numpy(sc.h).to(dev)
@@ -446,8 +446,8 @@ def bench_unrolled(cs, torch, dev, steps, warmup):
     k = 256), checkpoints every 10: forward (x_K and checkpoints) and
     backward (gradients of lam_t, tau_t and y from dL/dx_K)."""
     import workloads
-    prm = workloads.CFG5_PARAMS
-    c_np, xs_np = workloads.cfg5()
+    prm = workloads.SHARED_C_PARAMS
+    c_np, xs_np = workloads.shared_c_batch()
     K, every, d = prm["K"], prm["every"], 4
     n = c_np.shape[0]
     B = xs_np.shape[0]

@@ -189,21 +189,21 @@ def test_zero_iterations_and_bad_arguments():
 # sigma = 2, +-1 sensing kernel, rho = 1)
 # ----------------------------------------------------------------------------
 @pytest.fixture(scope="module")
-def cfg3():
-    pr = twod.build(workloads.cfg3(), workloads.CFG3_PARAMS["lam_frac"])
+def scene_2d():
+    pr = twod.build(workloads.scene_2d(), workloads.SCENE2D_PARAMS["lam_frac"])
     return pr, pr.op()
 
 
-def test_cfg3_operator_full_size(cfg3):
-    pr, op = cfg3
+def test_scene_2d_operator_full_size(scene_2d):
+    pr, op = scene_2d
     y = h_(cs.apply2(g(pr.s), g(pr.h), g(pr.x_true)))
     assert rel(y, pr.y.astype(np.float64)) <= OP_TOL
 
 
-def test_cfg3_first_iterates(cfg3):
-    pr, op = cfg3
+def test_scene_2d_first_iterates(scene_2d):
+    pr, op = scene_2d
     y = pr.y.astype(np.float64).ravel()
-    lam, rho = float(pr.lam), workloads.CFG3_PARAMS["rho"]
+    lam, rho = float(pr.lam), workloads.SCENE2D_PARAMS["rho"]
     _, hist = twod.admm(op, y, lam, rho, 3, record=True)
     sg, hg, yg = g(pr.s), g(pr.h), g(pr.y)
     for t in (1, 2, 3):
@@ -213,13 +213,13 @@ def test_cfg3_first_iterates(cfg3):
         assert (rel(z, zo) if np.any(zo) else np.abs(z).max()) <= IT_TOL, t
 
 
-def test_cfg3_full_run_trace(cfg3):
+def test_scene_2d_full_run_trace(scene_2d):
     """200 iterations: the GPU's trace ends at the oracle's FP64 objective of
     the returned x, and the trace decreases from F(x_1)."""
-    pr, op = cfg3
+    pr, op = scene_2d
     y = pr.y.astype(np.float64).ravel()
-    lam, rho = float(pr.lam), workloads.CFG3_PARAMS["rho"]
-    T = workloads.CFG3_PARAMS["admm_iters"]
+    lam, rho = float(pr.lam), workloads.SCENE2D_PARAMS["rho"]
+    T = workloads.SCENE2D_PARAMS["admm_iters"]
     obj = torch.empty(T, device=DEV, dtype=torch.float32)
     x, z, u = cs.admm_solve2(g(pr.s), g(pr.h), g(pr.y), pr.lam, rho, T, obj=obj)
     f = h_(obj)

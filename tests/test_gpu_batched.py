@@ -69,16 +69,16 @@ def test_batched_equals_plain_solver():
         assert rel(a, x) <= 1e-6
 
 
-def test_batched_cfg4_shape():
+def test_batched_uneven_batch_shape():
     """Sizes drawn like the batched workload (n = 2^12 .. 2^18, k = n/256),
     a smaller count; every signal checked at t = 100."""
-    sigs = workloads.cfg4(count=16)
+    sigs = workloads.uneven_batch(count=16)
     probs = batched.build_batch(sigs)
     T = 100
     got = run_batch(probs, 4, T)
     ref = batched.ista_batched(probs, T)
     worst = max(rel(a, b) for a, b in zip(got, ref))
-    print("cfg4-shaped batch worst rel err at t=100: %.3e" % worst)
+    print("uneven_batch-shaped batch worst rel err at t=100: %.3e" % worst)
     assert worst <= IT_TOL
 
 

@@ -33,8 +33,8 @@ def h(t):
 
 
 @pytest.fixture(scope="module")
-def cfg1():
-    pr = problem.build(workloads.cfg1())
+def parity_signal():
+    pr = problem.build(workloads.parity_signal())
     return pr, pr.A()
 
 
@@ -42,28 +42,28 @@ def trace(n):
     return torch.empty(n, device=DEV, dtype=torch.float32)
 
 
-def test_ista_trace_cfg1(cfg1):
-    pr, A = cfg1
+def test_ista_trace_parity_signal(parity_signal):
+    pr, A = parity_signal
     y = pr.y.astype(np.float64)
     lam, tau = float(pr.lam), float(pr.tau)
-    T = workloads.CFG1_PARAMS["ista_iters"]
+    T = workloads.PARITY_PARAMS["ista_iters"]
     _, hist = dense.ista(A, y, lam, tau, T, record=True)
     ref = np.array([dense.objective(A, y, lam, x) for x in hist])
     obj = trace(T)
     x = cs.ista_solve(g(pr.c), pr.d, g(pr.y), pr.lam, pr.tau, T, obj=obj)
     got = h(obj)
     err = np.abs(got - ref) / ref
-    print("ista trace cfg1: worst rel err %.2e (t=%d)" % (err.max(), err.argmax() + 1))
+    print("ista trace parity_signal: worst rel err %.2e (t=%d)" % (err.max(), err.argmax() + 1))
     assert err.max() <= F_TOL
     # the last entry is the objective of the returned iterate
     assert abs(got[-1] - dense.objective(A, y, lam, h(x))) <= F_TOL * ref[-1]
 
 
-def test_ista_trace_is_monotone(cfg1):
+def test_ista_trace_is_monotone(parity_signal):
     """tau <= 1/||A||^2: ISTA cannot increase the objective; FP32 may only
     wobble at the level of its round-off once the iterates stall."""
-    pr, _ = cfg1
-    T = workloads.CFG1_PARAMS["ista_iters"]
+    pr, _ = parity_signal
+    T = workloads.PARITY_PARAMS["ista_iters"]
     obj = trace(T)
     cs.ista_solve(g(pr.c), pr.d, g(pr.y), pr.lam, pr.tau, T, obj=obj)
     f = h(obj)
@@ -71,19 +71,19 @@ def test_ista_trace_is_monotone(cfg1):
     assert f[-1] < 0.5 * float(pr.y.astype(np.float64) @ pr.y.astype(np.float64))
 
 
-def test_admm_trace_cfg1(cfg1):
-    pr, A = cfg1
+def test_admm_trace_parity_signal(parity_signal):
+    pr, A = parity_signal
     y = pr.y.astype(np.float64)
     lam = float(pr.lam)
-    rho = workloads.CFG1_PARAMS["rho"]
-    T = workloads.CFG1_PARAMS["admm_iters"]
+    rho = workloads.PARITY_PARAMS["rho"]
+    T = workloads.PARITY_PARAMS["admm_iters"]
     _, hist = dense.admm(A, y, lam, rho, T, record=True)
     ref = np.array([dense.objective(A, y, lam, rec[0]) for rec in hist])
     obj = trace(T)
     cs.admm_solve(g(pr.c), pr.d, g(pr.y), pr.lam, rho, T, obj=obj)
     got = h(obj)
     err = np.abs(got - ref) / ref
-    print("admm trace cfg1: worst rel err %.2e (t=%d)" % (err.max(), err.argmax() + 1))
+    print("admm trace parity_signal: worst rel err %.2e (t=%d)" % (err.max(), err.argmax() + 1))
     assert err.max() <= F_TOL
 
 
@@ -105,10 +105,10 @@ def test_trace_other_shapes(n, d, k):
     assert np.max(np.abs(h(oa) - ra) / ra) <= F_TOL
 
 
-def test_trace_does_not_change_the_iterates(cfg1):
+def test_trace_does_not_change_the_iterates(parity_signal):
     """A trace switches to the two-launch schedule and adds reductions only:
     the iterates equal those of the two-launch schedule without a trace."""
-    pr, _ = cfg1
+    pr, _ = parity_signal
     c, yg = g(pr.c), g(pr.y)
     cs.set_solver_path(cs.PATH_TWO_PASS)
     try:
@@ -122,9 +122,9 @@ def test_trace_does_not_change_the_iterates(cfg1):
     assert all(np.array_equal(p, q) for p, q in zip(a0, a1))
 
 
-def test_trace_flags_non_finite_input(cfg1):
+def test_trace_flags_non_finite_input(parity_signal):
     """A NaN in y reaches the trace (the divergence guard a caller reads)."""
-    pr, _ = cfg1
+    pr, _ = parity_signal
     y = pr.y.copy()
     y[7] = np.nan
     obj = trace(5)
@@ -135,12 +135,12 @@ def test_trace_flags_non_finite_input(cfg1):
 def test_trace_full_size():
     """n = 2^22, d = 4: the first entries against the oracle's iterates, and
     the last entry against the oracle's FP64 objective of the returned x."""
-    pr = problem.build(workloads.cfg2())
+    pr = problem.build(workloads.large_signal())
     op = pr.op()
     y = pr.y.astype(np.float64)
     lam, tau = float(pr.lam), float(pr.tau)
     _, hist = fftref.ista(op, y, lam, tau, 3, record=True)
-    T = workloads.CFG2_PARAMS["ista_iters"]
+    T = workloads.LARGE_PARAMS["ista_iters"]
     obj = trace(T)
     x = cs.ista_solve(g(pr.c), pr.d, g(pr.y), pr.lam, pr.tau, T, obj=obj)
     got = h(obj)

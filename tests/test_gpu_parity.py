@@ -110,14 +110,14 @@ def test_apply_structured_inputs():
 # Solvers at the parity configuration (n = 4096, m = 1024, d = 4, k = 40)
 # ----------------------------------------------------------------------------
 @pytest.fixture(scope="module")
-def cfg1():
-    pr = problem.build(workloads.cfg1())
+def parity_signal():
+    pr = problem.build(workloads.parity_signal())
     A = pr.A()
     return pr, A
 
 
-def test_ista_per_iterate_cfg1(cfg1, path):
-    pr, A = cfg1
+def test_ista_per_iterate_parity_signal(parity_signal, path):
+    pr, A = parity_signal
     y = pr.y.astype(np.float64)
     lam, tau = float(pr.lam), float(pr.tau)
     _, hist = dense.ista(A, y, lam, tau, 100, record=True)
@@ -128,14 +128,14 @@ def test_ista_per_iterate_cfg1(cfg1, path):
         e = rel(x, hist[t - 1])
         worst = max(worst, e)
         assert e <= IT_TOL, (t, e)
-    print("ista cfg1 worst per-iterate rel err (t<=100): %.3e" % worst)
+    print("ista parity_signal worst per-iterate rel err (t<=100): %.3e" % worst)
 
 
-def test_ista_final_objective_cfg1(cfg1, path):
-    pr, A = cfg1
+def test_ista_final_objective_parity_signal(parity_signal, path):
+    pr, A = parity_signal
     y = pr.y.astype(np.float64)
     lam, tau = float(pr.lam), float(pr.tau)
-    T = workloads.CFG1_PARAMS["ista_iters"]
+    T = workloads.PARITY_PARAMS["ista_iters"]
     xo = dense.ista(A, y, lam, tau, T)
     x = h(cs.ista_solve(g(pr.c), pr.d, g(pr.y), pr.lam, pr.tau, T))
     fo, fg = dense.objective(A, y, lam, xo), dense.objective(A, y, lam, x)
@@ -143,11 +143,11 @@ def test_ista_final_objective_cfg1(cfg1, path):
     assert rel(x, xo) <= IT_TOL
 
 
-def test_admm_per_iterate_cfg1(cfg1, path):
-    pr, A = cfg1
+def test_admm_per_iterate_parity_signal(parity_signal, path):
+    pr, A = parity_signal
     y = pr.y.astype(np.float64)
     lam = float(pr.lam)
-    rho = workloads.CFG1_PARAMS["rho"]
+    rho = workloads.PARITY_PARAMS["rho"]
     _, hist = dense.admm(A, y, lam, rho, 100, record=True)
     c, yg = g(pr.c), g(pr.y)
     worst = 0.0
@@ -157,15 +157,15 @@ def test_admm_per_iterate_cfg1(cfg1, path):
         worst = max(worst, ex, ez)
         assert ex <= IT_TOL and ez <= IT_TOL, (t, ex, ez)
         assert eu <= 10 * IT_TOL, (t, eu)
-    print("admm cfg1 worst per-iterate rel err (t<=100): %.3e" % worst)
+    print("admm parity_signal worst per-iterate rel err (t<=100): %.3e" % worst)
 
 
-def test_admm_final_objective_cfg1(cfg1, path):
-    pr, A = cfg1
+def test_admm_final_objective_parity_signal(parity_signal, path):
+    pr, A = parity_signal
     y = pr.y.astype(np.float64)
     lam = float(pr.lam)
-    rho = workloads.CFG1_PARAMS["rho"]
-    T = workloads.CFG1_PARAMS["admm_iters"]
+    rho = workloads.PARITY_PARAMS["rho"]
+    T = workloads.PARITY_PARAMS["admm_iters"]
     (xo, zo, uo) = dense.admm(A, y, lam, rho, T)
     x, z, u = (h(v) for v in cs.admm_solve(g(pr.c), pr.d, g(pr.y), pr.lam, rho, T))
     fo, fg = dense.objective(A, y, lam, zo), dense.objective(A, y, lam, z)
@@ -211,24 +211,24 @@ def test_zero_iterations(path):
     assert np.all(h(z) == 4.0) and np.all(h(u) == 5.0)
 
 
-def test_lambda_at_lam_max_gives_zero(cfg1, path):
-    pr, A = cfg1
+def test_lambda_at_lam_max_gives_zero(parity_signal, path):
+    pr, A = parity_signal
     lmax = problem.lam_max(pr.c, pr.d, pr.y)
     lam = np.float32(lmax * 1.001)
     x = h(cs.ista_solve(g(pr.c), pr.d, g(pr.y), lam, pr.tau, 20))
     assert np.count_nonzero(x) == 0
 
 
-def test_lambda_zero_is_least_squares_gradient(cfg1, path):
+def test_lambda_zero_is_least_squares_gradient(parity_signal, path):
     """lam = 0: one ISTA step from 0 is tau A^T y exactly (no threshold)."""
-    pr, A = cfg1
+    pr, A = parity_signal
     x = h(cs.ista_solve(g(pr.c), pr.d, g(pr.y), 0.0, pr.tau, 1))
     ref = float(pr.tau) * (A.T @ pr.y.astype(np.float64))
     check_elementwise(x, ref)
 
 
-def test_admm_warm_start_continues(cfg1, path):
-    pr, A = cfg1
+def test_admm_warm_start_continues(parity_signal, path):
+    pr, A = parity_signal
     c, yg = g(pr.c), g(pr.y)
     x20, z20, u20 = (h(v) for v in cs.admm_solve(c, pr.d, yg, pr.lam, 1.0, 20))
     x, z, u = cs.admm_solve(c, pr.d, yg, pr.lam, 1.0, 10)
@@ -236,8 +236,8 @@ def test_admm_warm_start_continues(cfg1, path):
     assert rel(h(z), z20) <= 1e-6 and rel(h(u), u20) <= 1e-6 and rel(h(x), x20) <= 1e-6
 
 
-def test_deterministic(cfg1, path):
-    pr, A = cfg1
+def test_deterministic(parity_signal, path):
+    pr, A = parity_signal
     c, yg = g(pr.c), g(pr.y)
     a = h(cs.ista_solve(c, pr.d, yg, pr.lam, pr.tau, 50))
     b = h(cs.ista_solve(c, pr.d, yg, pr.lam, pr.tau, 50))
@@ -262,13 +262,13 @@ def test_bad_arguments_on_device():
 # Full size (n = 2^22, m = 2^20, d = 4), the benchmark's launch configuration
 # ----------------------------------------------------------------------------
 @pytest.fixture(scope="module")
-def cfg2():
-    pr = problem.build(workloads.cfg2())
+def large_signal():
+    pr = problem.build(workloads.large_signal())
     return pr, pr.op()
 
 
-def test_cfg2_ista_first_iterates(cfg2, path):
-    pr, op = cfg2
+def test_large_signal_ista_first_iterates(large_signal, path):
+    pr, op = large_signal
     y = pr.y.astype(np.float64)
     lam, tau = float(pr.lam), float(pr.tau)
     _, hist = fftref.ista(op, y, lam, tau, 3, record=True)
@@ -278,8 +278,8 @@ def test_cfg2_ista_first_iterates(cfg2, path):
         assert rel(x, hist[t - 1][1]) <= IT_TOL, t
 
 
-def test_cfg2_admm_first_iterates(cfg2, path):
-    pr, op = cfg2
+def test_large_signal_admm_first_iterates(large_signal, path):
+    pr, op = large_signal
     y = pr.y.astype(np.float64)
     lam = float(pr.lam)
     _, hist = fftref.admm(op, y, lam, 1.0, 3, record=True)
@@ -289,33 +289,33 @@ def test_cfg2_admm_first_iterates(cfg2, path):
         assert rel(x, hist[t - 1][1]) <= IT_TOL and rel(z, hist[t - 1][2]) <= IT_TOL, t
 
 
-def test_cfg2_operator_full_size(cfg2):
-    pr, op = cfg2
+def test_large_signal_operator_full_size(large_signal):
+    pr, op = large_signal
     y = h(cs.circ_apply(g(pr.c), pr.d, g(pr.x_true)))
     check_elementwise(y, pr.y.astype(np.float64), tol=OP_TOL)
 
 
-def test_cfg2_full_run_objective_decreases(cfg2, path):
+def test_large_signal_full_run_objective_decreases(large_signal, path):
     """At the benchmark's iteration counts the oracle cannot follow every
     iterate; the GPU iterates must still drive the FP64 objective down
     monotonically (ISTA with tau <= 1/||A||^2 cannot increase it)."""
-    pr, op = cfg2
+    pr, op = large_signal
     y = pr.y.astype(np.float64)
     lam = float(pr.lam)
     c, yg = g(pr.c), g(pr.y)
     f = [fftref.objective(op, y, lam, np.zeros(pr.n))]
-    for T in (10, 50, workloads.CFG2_PARAMS["ista_iters"]):
+    for T in (10, 50, workloads.LARGE_PARAMS["ista_iters"]):
         f.append(fftref.objective(op, y, lam, h(cs.ista_solve(c, pr.d, yg, pr.lam, pr.tau, T))))
     assert all(b < a for a, b in zip(f, f[1:])), f
-    x, z, u = cs.admm_solve(c, pr.d, yg, pr.lam, 1.0, workloads.CFG2_PARAMS["admm_iters"])
+    x, z, u = cs.admm_solve(c, pr.d, yg, pr.lam, 1.0, workloads.LARGE_PARAMS["admm_iters"])
     fz = fftref.objective(op, y, lam, h(z))
     assert fz < f[1]
 
 
-def test_paths_agree(cfg1):
+def test_paths_agree(parity_signal):
     """The persistent launch and the two-launch schedule run the same
     arithmetic in the same order: their iterates agree to FP32 round-off."""
-    pr, A = cfg1
+    pr, A = parity_signal
     c, yg = g(pr.c), g(pr.y)
     out = {}
     for p in (cs.PATH_TWO_PASS, cs.PATH_PERSISTENT):

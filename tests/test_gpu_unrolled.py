@@ -126,12 +126,12 @@ def test_autograd_function():
     check_grads((lt.grad, tt.grad, yt.grad), op, Y, lam, tau, K, Xs, amb, 1e-4)
 
 
-def test_cfg5_shape_forward_and_aggregate_gradients():
+def test_shared_c_batch_shape_forward_and_aggregate_gradients():
     """The differentiable workload's shape (n = 2^16, d = 4, k = 256, K = 50,
     checkpoints every 10) on 4 signals: the forward iterate per signal, and
     the lam / tau gradients, which aggregate over the batch."""
     n, d, K, every = 1 << 16, 4, 50, 10
-    c, Xs = workloads.cfg5(batch=4)
+    c, Xs = workloads.shared_c_batch(batch=4)
     op = fftref.Operator(c.astype(np.float64), d)
     Y = np.stack([op.A(x.astype(np.float64)) for x in Xs]).astype(np.float32)
     lam0 = 0.01 * np.mean([np.max(np.abs(op.AT(y.astype(np.float64)))) for y in Y])
@@ -144,7 +144,7 @@ def test_cfg5_shape_forward_and_aggregate_gradients():
     # effect on the gradients is of order 1e-6 (relative), far below the bar
     gl, gt, gy = cs.unrolled_ista_bwd(g(c), d, g(Y), g(lam), g(tau), K, every, ckpt, g(2.0 * (XK - Xs)))
     rl, rt, ry = unrolled.backward(op, Y.astype(np.float64), lam.astype(np.float64), tau.astype(np.float64), K, Xs)
-    print("cfg5-shaped: rel err lam %.2e tau %.2e y %.2e" % (rel(h(gl), rl), rel(h(gt), rt), rel(h(gy), ry)))
+    print("shared_c_batch-shaped: rel err lam %.2e tau %.2e y %.2e" % (rel(h(gl), rl), rel(h(gt), rt), rel(h(gy), ry)))
     assert rel(h(gl), rl) <= 1e-3 and rel(h(gt), rt) <= 1e-3 and rel(h(gy), ry) <= 1e-3
 
 

@@ -340,10 +340,10 @@ def test_P12_brute_force_n8():
 
 
 # --------------------------------------------------------------------------
-# P13: at cfg1's shape the converged support equals the true support.
+# P13: at parity_signal's shape the converged support equals the true support.
 # --------------------------------------------------------------------------
-def test_P13_cfg1_support_recovery():
-    sig = workloads.cfg1()
+def test_P13_parity_signal_support_recovery():
+    sig = workloads.parity_signal()
     pr = problem.build(sig)
     op = pr.op()
     (x, z, u) = fftref.admm(op, pr.y.astype(np.float64), float(pr.lam), 1.0, 3000)
@@ -374,8 +374,8 @@ def test_P14_ista_monotone():
 # The FFT reference reproduces the dense iterates (gives it authority at the
 # sizes where a dense A is impossible).
 # --------------------------------------------------------------------------
-def test_fftref_iterates_match_dense_cfg1():
-    sig = workloads.cfg1()
+def test_fftref_iterates_match_dense_parity_signal():
+    sig = workloads.parity_signal()
     pr = problem.build(sig)
     A = pr.A()
     op = pr.op()
@@ -391,7 +391,7 @@ def test_fftref_iterates_match_dense_cfg1():
 
 
 def test_problem_rounding_rule():
-    sig = workloads.cfg1()
+    sig = workloads.parity_signal()
     pr = problem.build(sig)
     assert pr.y.dtype == np.float32 and pr.c.dtype == np.float32
     assert isinstance(pr.lam, np.float32) and isinstance(pr.tau, np.float32)

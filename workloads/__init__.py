@@ -6,15 +6,17 @@ no thresholds.  Both the FP64 oracle (tests) and the HIP path (tests, bench)
 take their inputs from here, so neither needs the other to build a workload.
 
 Workload shapes follow the paper's synthetic experiments (Section 6: Gaussian
-nonzeros at random positions, a Gaussian circulant generator) at the sizes of
-the five configurations below:
+nonzeros at random positions, a Gaussian circulant generator) at these sizes:
 
-  cfg1  n=4096,  d=4,  k=40         parity case
-  cfg2  n=2^22,  d=4,  k=2^14       large single signal
-  cfg3  4096x4096 scene, 20000 lognormal point sources, +-1 2-D sensing
-        kernel, sigma=2 Gaussian PSF truncated to 15x15, 2x decimation per axis
-  cfg4  512 signals, n_i = 2^e, e uniform in {12..18}, d=4, k_i=n_i/256
-  cfg5  shared generator, n=2^16, d=4, batch 64 signals with k=256
+  parity_signal   n=4096, d=4, k=40: the parity case
+  large_signal    n=2^22, d=4, k=2^14: the large single signal
+  scene_2d        4096x4096 scene, 20000 lognormal point sources, +-1 2-D
+                  sensing kernel, sigma=2 Gaussian PSF truncated to 15x15,
+                  2x decimation per axis
+  uneven_batch    512 signals, n_i = 2^e, e uniform in {12..18}, d=4,
+                  k_i=n_i/256
+  shared_c_batch  shared generator, n=2^16, d=4, batch 64 signals with k=256
+  deblur_field    1024x1024 field vectorised, 10% lognormal pixels, d=2
 
 Every draw is made in float64 and then rounded to float32 (the arrays handed to
 both sides are those float32 values).  The generator c has entries
@@ -65,16 +67,16 @@ def signal(n: int, d: int, k: int, seed: int) -> Signal1D:
     return draw_1d(np.random.default_rng(seed), n, d, k)
 
 
-def cfg1(seed_offset: int = 0) -> Signal1D:
+def parity_signal(seed_offset: int = 0) -> Signal1D:
     return draw_1d(np.random.default_rng(SEED_BASE + 1 + seed_offset), 4096, 4, 40)
 
 
-def cfg2(seed_offset: int = 0) -> Signal1D:
+def large_signal(seed_offset: int = 0) -> Signal1D:
     return draw_1d(np.random.default_rng(SEED_BASE + 2 + seed_offset), 1 << 22, 4, 1 << 14)
 
 
-CFG1_PARAMS = dict(ista_iters=500, admm_iters=200, rho=1.0, lam_frac=0.01)
-CFG2_PARAMS = dict(ista_iters=300, admm_iters=100, rho=1.0, lam_frac=0.01)
+PARITY_PARAMS = dict(ista_iters=500, admm_iters=200, rho=1.0, lam_frac=0.01)
+LARGE_PARAMS = dict(ista_iters=300, admm_iters=100, rho=1.0, lam_frac=0.01)
 
 
 @dataclasses.dataclass
@@ -116,14 +118,14 @@ def draw_2d(rng: np.random.Generator, n1: int, n2: int, n_src: int,
                    x_true=_f32(x.reshape(n1, n2)))
 
 
-def cfg3(seed_offset: int = 0) -> Scene2D:
+def scene_2d(seed_offset: int = 0) -> Scene2D:
     return draw_2d(np.random.default_rng(SEED_BASE + 3 + seed_offset), 4096, 4096, 20000)
 
 
-CFG3_PARAMS = dict(admm_iters=200, rho=1.0, lam_frac=0.005)
+SCENE2D_PARAMS = dict(admm_iters=200, rho=1.0, lam_frac=0.005)
 
 
-def cfg4(seed_offset: int = 0, count: int = 512, e_lo: int = 12, e_hi: int = 18):
+def uneven_batch(seed_offset: int = 0, count: int = 512, e_lo: int = 12, e_hi: int = 18):
     """Batched uneven sizes: all exponents first, then each signal's draws in
     the 1-D order (c, support, values); k_i = n_i/256."""
     rng = np.random.default_rng(SEED_BASE + 4 + seed_offset)
@@ -135,10 +137,10 @@ def cfg4(seed_offset: int = 0, count: int = 512, e_lo: int = 12, e_hi: int = 18)
     return out
 
 
-CFG4_PARAMS = dict(ista_iters=200, lam_frac=0.01)
+UNEVEN_PARAMS = dict(ista_iters=200, lam_frac=0.01)
 
 
-def cfg5(seed_offset: int = 0, n: int = 1 << 16, d: int = 4, batch: int = 64, k: int = 256):
+def shared_c_batch(seed_offset: int = 0, n: int = 1 << 16, d: int = 4, batch: int = 64, k: int = 256):
     """Shared generator c, then `batch` sparse truths (support, values)."""
     rng = np.random.default_rng(SEED_BASE + 5 + seed_offset)
     m = n // d
@@ -150,7 +152,7 @@ def cfg5(seed_offset: int = 0, n: int = 1 << 16, d: int = 4, batch: int = 64, k:
     return c, _f32(xs)
 
 
-CFG5_PARAMS = dict(K=50, every=10, lam_frac=0.01)
+SHARED_C_PARAMS = dict(K=50, every=10, lam_frac=0.01)
 
 
 def deblur_field(seed_offset: int = 0, side: int = 1024, frac: float = 0.1):
