@@ -115,3 +115,22 @@ def test_bad_2d_arguments_rejected():
     assert lib.cs2_admm_solve(FAKE, NULL, 64, 64, FAKE, 0.1, 0.0, 5, 0, FAKE, FAKE, FAKE, NULL, NULL) == _lib.CS_EINVAL
     assert lib.cs2_admm_solve(FAKE, NULL, 64, 64, FAKE, 0.1, 1.0, -2, 0, FAKE, FAKE, FAKE, NULL, NULL) == _lib.CS_EINVAL
     assert b"rows" in lib.cs_last_error() or b"iters" in lib.cs_last_error()
+
+
+@pytest.mark.parametrize("n,d", [(1000, 4), (4096, 3), (4096, 1), (128, 2)])
+def test_direct_products_reject_bad_sizes(n, d):
+    """The direct products validate like the FFT operators: nothing is
+    enqueued for a size the library does not support."""
+    lib = _lib.load()
+    assert lib.cs_circ_apply_direct(FAKE, n, d, FAKE, FAKE, NULL) == _lib.CS_EINVAL
+    assert lib.cs_circ_apply_T_direct(FAKE, n, d, FAKE, FAKE, NULL) == _lib.CS_EINVAL
+    assert lib.cs_last_error() != b""
+
+
+def test_direct_products_reject_null_pointers():
+    lib = _lib.load()
+    assert lib.cs_circ_apply_direct(NULL, 4096, 4, FAKE, FAKE, NULL) == _lib.CS_EINVAL
+    assert lib.cs_circ_apply_direct(FAKE, 4096, 4, NULL, FAKE, NULL) == _lib.CS_EINVAL
+    assert lib.cs_circ_apply_direct(FAKE, 4096, 4, FAKE, NULL, NULL) == _lib.CS_EINVAL
+    assert lib.cs_circ_apply_T_direct(FAKE, 4096, 4, NULL, FAKE, NULL) == _lib.CS_EINVAL
+    assert lib.cs_circ_apply_T_direct(FAKE, 4096, 4, FAKE, NULL, NULL) == _lib.CS_EINVAL
