@@ -119,12 +119,17 @@ cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, fl
  * tau_dev[i] (device arrays of `count` floats) and output / iterate
  * x_cat[off_n_host[i] .. + n); d (2, 4 or 8) is shared.  n_host and the
  * offsets are HOST arrays; off_n must be even.  Output slices must not
- * overlap.  Each signal is solved exactly as cs_ista_solve would (same
- * arithmetic), from x(0) = 0, for `iters` iterations.  Workgroups take whole
- * signals from a work queue, longest first; the launch is one kernel and can
- * be captured in a HIP graph.  A per-device scratch area (about 3n complex
- * per signal) is allocated on first use and grown when a larger batch comes;
- * batched calls on one device must be serialised.  */
+ * overlap.  Each signal is solved with the same arithmetic as cs_ista_solve,
+ * from x(0) = 0, for `iters` iterations.  Signals with n < 2^15 are solved
+ * in one launch whose workgroups take whole signals from a work queue,
+ * longest first; longer signals are grouped by length, and each group runs
+ * the row and column passes over all its signals at once (two launches per
+ * iteration, plus a gather of the group's inputs and a scatter of its
+ * outputs).  Per-device scratch (about 3n complex per short signal; for the
+ * groups, copies and tables of at most 2 GiB at a time) is allocated on
+ * first use and grown when a larger batch comes, and signal descriptors are
+ * uploaded with a synchronous copy when they change; batched calls on one
+ * device must be serialised.  */
 cs_status cs_ista_solve_batched(int32_t count, const int64_t* n_host, int32_t d, const int64_t* off_n_host,
                                 const int64_t* off_m_host, const float* c_cat, const float* y_cat,
                                 const float* lambda_dev, const float* tau_dev, int32_t iters, float* x_cat,
