@@ -16,9 +16,9 @@
 // Forward: thread t owns outputs i0 + t + q*T (q < RO), so for a block of four
 // inputs the four c values of one output are contiguous (one 16-byte LDS
 // read per four multiply-adds, consecutive lanes 4d bytes apart) and the four
-// inputs are a broadcast read.  Transpose: thread t owns outputs
-// j0 + t + q*T; for one input i the lanes read consecutive c values (one
-// 4-byte read per multiply-add, conflict-free) and r_i is a broadcast.
+// inputs are a broadcast read.  Transpose: a register sliding window along
+// the d-strided diagonals (one 4-byte LDS read per RO multiply-adds, see
+// k_direct_adj) with r_i a broadcast.
 // Accumulation is in FP32, in input order.  The next tile's window and inputs
 // are loaded into registers while the current tile is computed, so the
 // global loads of the staging overlap the multiply-adds.
@@ -120,21 +120,46 @@ __global__ __launch_bounds__(kDirT) void k_direct_fwd(const float* __restrict__ 
 }
 
 // x = A^T r.  Grid: ceil(n / kDirOutT) workgroups of kDirT threads.
+//
+// Thread t = a + D b (a < D) owns outputs j0 + a + D (b RO + q), q < RO.  For
+// input i0 + ii its c index is u = D (ii - b RO - q) - a + kDirOutT - 1: all of
+// a thread's indices share the residue D - 1 - a of u mod D, and along
+// w = ii - q they are consecutive in u / D, so the values of one thread form a
+// sliding window: each new input brings one new value and the other RO - 1
+// are reused from registers (one LDS read per RO multiply-adds).  The c
+// window is stored split by residue class, each class padded with one word
+// per 2^SH and offset by a per-d extra stride, which makes the reads of the
+// 64 lanes of a wave hit 64 distinct banks for every d (checked on the host
+// with a bank model).
+template <int D>
+struct DirAdjLayout {
+  static constexpr int SH = (D == 2) ? 2 : 3;
+  static constexpr int XS = (D == 2) ? 1 : (D == 4) ? 8 : (D == 8) ? 0 : 4;
+  static constexpr int LV = kDirOutT / D + kDirTileI;          // u / D range of the window
+  static constexpr int LVP = LV + (LV >> SH) + 8 + XS;         // padded length of one class
+  __device__ static int pv(int v) { return v + (v >> SH); }
+};
+
 template <int D>
 __global__ __launch_bounds__(kDirT) void k_direct_adj(const float* __restrict__ c, const float* __restrict__ r,
                                                       float* __restrict__ x, long long n) {
+  using Lay = DirAdjLayout<D>;
   constexpr int RO = kDirOutT / kDirT;
   __shared__ float rs[kDirTileI];
-  __shared__ float cw[D * kDirTileI + kDirOutT];
+  __shared__ float cw[D * Lay::LVP];
   const long long m = n / D;
   const long long j0 = (long long)blockIdx.x * kDirOutT;
   const int tid = threadIdx.x;
   const int tile = m < kDirTileI ? (int)m : kDirTileI;
   const long long mask = n - 1;
+  const int a = tid % D, b = tid / D;
+  const float* cr = cw + (D - 1 - a) * Lay::LVP;
+  const int vb = kDirOutT / D - 1 - b * RO;   // u / D of (ii, q) is vb + ii - q
   float acc[RO];
 #pragma unroll
   for (int q = 0; q < RO; ++q) acc[q] = 0.0f;
-  // window of tile i0: cw[u] = c[(D i0 - j0 - kDirOutT + 1 + u) mod n], u < D tile + kDirOutT
+  // window of tile i0: c[(D i0 - j0 - kDirOutT + 1 + u) mod n] for
+  // u < D tile + kDirOutT, stored at cw[(u mod D) LVP + pv(u / D)]
   constexpr int NW = (D * kDirTileI + kDirOutT) / kDirT;
   constexpr int NR = kDirTileI / kDirT;
   float pw[NW], pr[NR];
@@ -156,7 +181,7 @@ __global__ __launch_bounds__(kDirT) void k_direct_adj(const float* __restrict__ 
 #pragma unroll
     for (int k = 0; k < NW; ++k) {
       const int u = tid + k * kDirT;
-      if (u < D * tile + kDirOutT) cw[u] = pw[k];
+      if (u < D * tile + kDirOutT) cw[(u % D) * Lay::LVP + Lay::pv(u / D)] = pw[k];
     }
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
@@ -165,17 +190,28 @@ __global__ __launch_bounds__(kDirT) void k_direct_adj(const float* __restrict__ 
     }
     __syncthreads();
     if (i0 + tile < m) fetch(i0 + tile);
-    // input i = i0 + ii, output j = j0 + tid + q T:  u = D ii - (tid + q T) + kDirOutT - 1
-    for (int ii = 0; ii < tile; ++ii) {
-      const float rv = rs[ii];
+    // prev[RO + w] holds the value at w = ii - q < 0 of the current chunk
+    float prev[RO];
 #pragma unroll
-      for (int q = 0; q < RO; ++q) acc[q] = fmaf(cw[D * ii - (tid + q * kDirT) + kDirOutT - 1], rv, acc[q]);
+    for (int w = 1; w < RO; ++w) prev[RO - w] = cr[Lay::pv(vb - w)];
+    for (int ii0 = 0; ii0 < tile; ii0 += RO) {
+      float cur[RO];
+#pragma unroll
+      for (int s = 0; s < RO; ++s) cur[s] = cr[Lay::pv(vb + ii0 + s)];
+#pragma unroll
+      for (int s = 0; s < RO; ++s) {
+        const float rv = rs[ii0 + s];
+#pragma unroll
+        for (int q = 0; q < RO; ++q) acc[q] = fmaf(s >= q ? cur[s - q] : prev[RO + s - q], rv, acc[q]);
+      }
+#pragma unroll
+      for (int s = 1; s < RO; ++s) prev[s] = cur[s];
     }
     __syncthreads();
   }
 #pragma unroll
   for (int q = 0; q < RO; ++q) {
-    const long long j = j0 + tid + (long long)q * kDirT;
+    const long long j = j0 + a + (long long)D * (b * RO + q);
     if (j < n) x[j] = acc[q];
   }
 }
