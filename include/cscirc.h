@@ -120,7 +120,7 @@ cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, fl
  * x_cat[off_n_host[i] .. + n); d (2, 4 or 8) is shared.  n_host and the
  * offsets are HOST arrays; off_n must be even.  Output slices must not
  * overlap.  Each signal is solved with the same arithmetic as cs_ista_solve,
- * from x(0) = 0, for `iters` iterations.  Signals with n < 2^15 are solved
+ * from x(0) = 0, for `iters` iterations.  Signals with n < 2^14 are solved
  * in one launch whose workgroups take whole signals from a work queue,
  * longest first; longer signals are grouped by length, and each group runs
  * the row and column passes over all its signals at once (two launches per

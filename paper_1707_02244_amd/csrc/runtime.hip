@@ -446,7 +446,7 @@ struct BatchState {
 // Signals from this length on are solved per length group (see
 // cs_ista_solve_batched).
 #ifndef CS_GROUP_MIN_LOGN
-#define CS_GROUP_MIN_LOGN 15
+#define CS_GROUP_MIN_LOGN 14
 #endif
 constexpr int64_t kGroupMinN = int64_t(1) << CS_GROUP_MIN_LOGN;
 constexpr size_t kGroupChunkBytes = size_t(1) << 31;
