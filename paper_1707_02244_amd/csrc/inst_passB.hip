@@ -37,6 +37,7 @@ hipError_t launch_ucol<CS_LEN>(int mode, int grid, int batch, const PassBArgs& a
     case B_ISTA_REC: k_ucol<L, B_ISTA_REC><<<g, b, 0, s>>>(a, st); break;
     case B_ADJ_V: k_ucol<L, B_ADJ_V><<<g, b, 0, s>>>(a, st); break;
     case B_ADJ_X: k_ucol<L, B_ADJ_X><<<g, b, 0, s>>>(a, st); break;
+    case B_ADJ_XV: k_ucol<L, B_ADJ_XV><<<g, b, 0, s>>>(a, st); break;
     case B_OUT_DEC: k_ucol<L, B_OUT_DEC><<<g, b, 0, s>>>(a, st); break;
     default: return hipErrorInvalidValue;
   }

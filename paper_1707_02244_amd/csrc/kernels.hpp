@@ -77,6 +77,8 @@ enum ModeB : int {
   B_ISTA_REC = 7,  // B_ISTA that also records v_t = x + step and the step
   B_ADJ_V = 8,     // xbar -> vbar = M_t * xbar, partial sums -> forward -> Y
   B_ADJ_X = 9,     // Y -> inverse -> xbar = vbar + (-tau A^T A vbar)
+  B_ADJ_XV = 10,   // B_ADJ_X of step t fused with B_ADJ_V of step t-1: xbar_{t-1}
+                   //   stays in registers (a.t, rv, rd, part are step t-1's)
 };
 
 struct PassAArgs {
@@ -414,6 +416,36 @@ __global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
 // interleaved, element (column c, index i) at [i*CB + c].  Global accesses are
 // issued in register-staged chunks of CH elements per thread so that a chunk's
 // loads are all in flight before the first wait.
+// Adjoint mask of one pair of samples: vbar = M_t * xbar with
+// M_t = 1[|v_t| > theta_t]; accumulates -sgn(v_t) vbar_t (the threshold's
+// derivative) and vbar_t * step_t (the step's, step_t = tau_t g_t) in double.
+__device__ __forceinline__ float2 adj_mask(float2 xb, float2 v, float2 st, float thr, double& s_th, double& s_g) {
+  const float2 vb = c2(fabsf(v.x) > thr ? xb.x : 0.0f, fabsf(v.y) > thr ? xb.y : 0.0f);
+  s_th -= double(v.x > 0.0f ? vb.x : -vb.x) + double(v.y > 0.0f ? vb.y : -vb.y);
+  s_g += double(vb.x) * double(st.x) + double(vb.y) * double(st.y);
+  return vb;
+}
+
+// Workgroup sums of the two adjoint partials (wave shuffles, then one value
+// per wave), written to part[0] and part[part_q].  All threads call it.
+template <int T>
+__device__ __forceinline__ void adj_partials(const PassBArgs& a, double s_th, double s_g, unsigned tid) {
+  __shared__ double red[2][T / 64];
+  for (int off = 32; off > 0; off >>= 1) {
+    s_th += __shfl_xor(s_th, off);
+    s_g += __shfl_xor(s_g, off);
+  }
+  if ((tid & 63) == 0) { red[0][tid >> 6] = s_th; red[1][tid >> 6] = s_g; }
+  __syncthreads();
+  if (tid == 0) {
+    double r0 = 0.0, r1 = 0.0;
+    for (int w = 0; w < T / 64; ++w) { r0 += red[0][w]; r1 += red[1][w]; }
+    a.part[0] = r0;
+    a.part[a.part_q] = r1;
+  }
+  __syncthreads();
+}
+
 template <int N1, int MODE, int T>
 __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __restrict__ lds,
                                         const float2* __restrict__ tws, unsigned tid) {
@@ -425,7 +457,7 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
   const int j2_0 = blk * CB;
   const int N2 = a.N2;
   constexpr bool HAS_INV = (MODE == B_ISTA || MODE == B_ADMM || MODE == B_OUT_ALL || MODE == B_OUT_DEC ||
-                            MODE == B_ISTA_REC || MODE == B_ADJ_X);
+                            MODE == B_ISTA_REC || MODE == B_ADJ_X || MODE == B_ADJ_XV);
 
   if constexpr (HAS_INV) {
 #pragma unroll
@@ -510,6 +542,19 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
         reinterpret_cast<float2*>(a.xbar)[j] = cadd(reinterpret_cast<const float2*>(a.vbar)[j], lds[lp(i)]);
       }
       fwd = false;
+    } else if constexpr (MODE == B_ADJ_XV) {
+      // xbar_{t-1} = vbar_t + lds, then step t-1's mask and sums in place
+      const float thr = a.tau_dev[a.t] * a.lam_dev[a.t];
+      double s_th = 0.0, s_g = 0.0;
+      for (int i = tid; i < NE; i += T) {
+        const size_t j = (size_t)(i / CB) * N2 + j2_0 + (i % CB);
+        const float2 xb = cadd(reinterpret_cast<const float2*>(a.vbar)[j], lds[lp(i)]);
+        const float2 vb = adj_mask(xb, reinterpret_cast<const float2*>(a.rv)[j],
+                                   reinterpret_cast<const float2*>(a.rd)[j], thr, s_th, s_g);
+        reinterpret_cast<float2*>(a.vbar)[j] = vb;
+        lds[lp(i)] = vb;
+      }
+      adj_partials<T>(a, s_th, s_g, tid);
     } else if constexpr (MODE == B_OUT_ALL) {
       for (int i = tid; i < NE; i += T) {
         const int j1 = i / CB, c = i % CB;
@@ -536,30 +581,12 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
     double s_th = 0.0, s_g = 0.0;
     for (int i = tid; i < NE; i += T) {
       const size_t j = (size_t)(i / CB) * N2 + j2_0 + (i % CB);
-      const float2 xb = reinterpret_cast<const float2*>(a.xbar)[j];
-      const float2 v = reinterpret_cast<const float2*>(a.rv)[j];
-      const float2 st = reinterpret_cast<const float2*>(a.rd)[j];
-      const float2 vb = c2(fabsf(v.x) > thr ? xb.x : 0.0f, fabsf(v.y) > thr ? xb.y : 0.0f);
-      s_th -= double(v.x > 0.0f ? vb.x : -vb.x) + double(v.y > 0.0f ? vb.y : -vb.y);
-      s_g += double(vb.x) * double(st.x) + double(vb.y) * double(st.y);
+      const float2 vb = adj_mask(reinterpret_cast<const float2*>(a.xbar)[j], reinterpret_cast<const float2*>(a.rv)[j],
+                                 reinterpret_cast<const float2*>(a.rd)[j], thr, s_th, s_g);
       reinterpret_cast<float2*>(a.vbar)[j] = vb;
       lds[lp(i)] = vb;
     }
-    // workgroup reduction: wave sums by shuffles, then one value per wave
-    __shared__ double red[2][T / 64];
-    for (int off = 32; off > 0; off >>= 1) {
-      s_th += __shfl_xor(s_th, off);
-      s_g += __shfl_xor(s_g, off);
-    }
-    if ((tid & 63) == 0) { red[0][tid >> 6] = s_th; red[1][tid >> 6] = s_g; }
-    __syncthreads();
-    if (tid == 0) {
-      double r0 = 0.0, r1 = 0.0;
-      for (int w = 0; w < T / 64; ++w) { r0 += red[0][w]; r1 += red[1][w]; }
-      a.part[0] = r0;
-      a.part[a.part_q] = r1;
-    }
-    __syncthreads();
+    adj_partials<T>(a, s_th, s_g, tid);
   } else {
 #pragma unroll
     for (int k0 = 0; k0 < EPT; k0 += CH) {

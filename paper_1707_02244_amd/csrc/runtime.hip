@@ -977,21 +977,36 @@ cs_status cs_unrolled_ista_bwd(const float* c, int64_t n, int32_t d, int32_t Bt,
       b.rd = U->rd + size_t(t - t0) * BN;
       CS_LAUNCH(launchUB(*P, B_ISTA_REC, Bt, b, us, s));
     }
-    // reverse through the segment
-    for (int t = t1 - 1; t >= t0; --t) {
-      PassBArgs b = argsB(*P);
-      b.Y = U->Y; b.xbar = U->xbar; b.vbar = U->vbar; b.tau_dev = tau; b.lam_dev = lam; b.t = t;
-      b.rv = U->rv + size_t(t - t0) * BN;
-      b.rd = U->rd + size_t(t - t0) * BN;
-      b.part = U->part + size_t(t) * 2 * size_t(Bt) * size_t(nblk);
+    // reverse through the segment.  Step t's mask and sums (B_ADJ_V) read
+    // xbar_t; inside the segment they are fused with step t+1's xbar update
+    // (B_ADJ_XV), so xbar is stored only where a segment starts (B_ADJ_X),
+    // for the step that follows the previous segment's recompute.
+    auto adj_args = [&](int tt, PassBArgs& b) {
+      b.tau_dev = tau; b.lam_dev = lam; b.t = tt;
+      b.rv = U->rv + size_t(tt - t0) * BN;
+      b.rd = U->rd + size_t(tt - t0) * BN;
+      b.part = U->part + size_t(tt) * 2 * size_t(Bt) * size_t(nblk);
       b.part_q = Bt * nblk;
+    };
+    {
+      PassBArgs b = argsB(*P);
+      b.Y = U->Y; b.xbar = U->xbar; b.vbar = U->vbar;
+      adj_args(t1 - 1, b);
       CS_LAUNCH(launchUB(*P, B_ADJ_V, Bt, b, us, s));
+    }
+    for (int t = t1 - 1; t >= t0; --t) {
       PassAArgs a = argsA(*P);
       a.Y = U->Y; a.ybar = U->ybar; a.tau_dev = tau; a.t = t;
       CS_LAUNCH(launchUA(*P, A_ADJ, Bt, a, us, s));
       PassBArgs bx = argsB(*P);
-      bx.Y = U->Y; bx.xbar = U->xbar; bx.vbar = U->vbar;
-      CS_LAUNCH(launchUB(*P, B_ADJ_X, Bt, bx, us, s));
+      bx.Y = U->Y; bx.vbar = U->vbar;
+      if (t > t0) {
+        adj_args(t - 1, bx);
+        CS_LAUNCH(launchUB(*P, B_ADJ_XV, Bt, bx, us, s));
+      } else {
+        bx.xbar = U->xbar;
+        CS_LAUNCH(launchUB(*P, B_ADJ_X, Bt, bx, us, s));
+      }
     }
   }
   k_unrolled_grads<<<dim3(K), dim3(256), 0, s>>>(U->part, Bt * nblk, tau, lam, g_lam, g_tau);
