@@ -104,3 +104,21 @@ def test_direct_bad_arguments():
         cs.circ_apply_direct(c, 3, g(np.ones(1024)), g(np.ones(341)))
     with pytest.raises(cs.CsError):
         cs.circ_apply_T_direct(g(np.ones(1000)), 4, g(np.ones(250)))
+
+
+def test_direct_headline_size():
+    """The products the direct baseline times (n = 2^22, m = 2^20, d = 4, the
+    headline's c, x and y) against the FP64 FFT oracle, every output.  FP32
+    accumulation in input order of N terms errs by about u sqrt(N) relative
+    (u = 2^-24): N = 2^14 nonzeros of x for A x, N = m for A^T y; the bound
+    is three times that."""
+    pr = problem.build(workloads.large_signal())
+    n, d = pr.n, pr.d
+    op = pr.op()
+    c = g(pr.c)
+    u = 2.0 ** -24
+    y = h(cs.circ_apply_direct(c, d, g(pr.x_true)))
+    k = int(np.count_nonzero(pr.x_true))
+    assert rel(y, op.A(pr.x_true.astype(np.float64))) <= 3 * u * np.sqrt(k)
+    xt = h(cs.circ_apply_T_direct(c, d, g(pr.y)))
+    assert rel(xt, op.AT(pr.y.astype(np.float64))) <= 3 * u * np.sqrt(n // d)
