@@ -138,3 +138,23 @@ def test_batched_groups_repeat_and_reorder():
     c = run_batch([probs[i] for i in perm], d, 15)
     for k, i in enumerate(perm):
         assert np.array_equal(c[k], a[i])
+
+
+def test_batched_full_workload_sampled():
+    """The timed configuration itself: all 512 signals of the uneven batch
+    (n_i = 2^12 .. 2^18, d = 4) in one call, 200 iterations, so the work
+    queue and every length group run as in the benchmark; the first signal
+    of each length and the last signal of the batch against the oracle."""
+    sigs = workloads.uneven_batch()
+    probs = batched.build_batch(sigs, workloads.UNEVEN_PARAMS["lam_frac"])
+    T = workloads.UNEVEN_PARAMS["ista_iters"]
+    got = run_batch(probs, 4, T)
+    ns = [p.n for p in probs]
+    pick = sorted({ns.index(n) for n in set(ns)} | {len(ns) - 1})
+    assert len(set(ns[i] for i in pick)) == 7
+    worst = 0.0
+    for i in pick:
+        e = rel(got[i], batched.ista_one(probs[i], T))
+        worst = max(worst, e)
+        assert e <= IT_TOL, (i, ns[i], e)
+    print("full uneven batch, %d sampled signals, worst rel err at t=%d: %.3e" % (len(pick), T, worst))
