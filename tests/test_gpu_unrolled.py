@@ -158,3 +158,42 @@ def test_unrolled_bad_arguments():
         cs.unrolled_ista_fwd(c, 3, g(np.ones((2, 1024 // 3))), lam, lam, 5, 2)
     with pytest.raises(cs.CsError):
         cs.unrolled_ista_fwd(c, 4, y, g(np.zeros(0)), g(np.zeros(0)), 0, 2)
+
+
+def test_shared_c_batch_full_size_sampled():
+    """The timed configuration itself: all 64 signals (n = 2^16, d = 4,
+    K = 50, checkpoints every 10) in one forward and one backward call.
+    Sampled signals against the oracle (x_K and the y gradient of each are
+    that signal's own); the lam / tau gradients, sums over the batch, equal
+    the sums of the gradients of the two halves of the batch."""
+    prm = workloads.SHARED_C_PARAMS
+    K, every, d = prm["K"], prm["every"], 4
+    c, Xs = workloads.shared_c_batch()
+    B = Xs.shape[0]
+    op = fftref.Operator(c.astype(np.float64), d)
+    Y = np.stack([op.A(x.astype(np.float64)) for x in Xs]).astype(np.float32)
+    lam0 = prm["lam_frac"] * max(float(np.max(np.abs(op.AT(y.astype(np.float64))))) for y in Y)
+    lam = np.full(K, lam0, np.float32)
+    tau = np.full(K, 1.0 / op.max_chat_sq(), np.float32)
+    xK, ckpt = cs.unrolled_ista_fwd(g(c), d, g(Y), g(lam), g(tau), K, every)
+    xK = h(xK)
+    pick = [0, 21, 42, B - 1]
+    args = (lam.astype(np.float64), tau.astype(np.float64), K)
+    XKs, _ = unrolled.forward(op, Y[pick].astype(np.float64), *args)
+    for j, b in enumerate(pick):
+        assert rel(xK[b], XKs[j]) <= 1e-4, (b, rel(xK[b], XKs[j]))
+    # the sampled signals' loss gradient is the oracle's, the others' the GPU's
+    gx = 2.0 * (xK - Xs)
+    gx[pick] = 2.0 * (XKs - Xs[pick])
+    gl, gt, gy = (h(v) for v in cs.unrolled_ista_bwd(g(c), d, g(Y), g(lam), g(tau), K, every, ckpt, g(gx)))
+    _, _, ry = unrolled.backward(op, Y[pick].astype(np.float64), *args, Xs[pick])
+    for j, b in enumerate(pick):
+        assert rel(gy[b], ry[j]) <= 1e-3, (b, rel(gy[b], ry[j]))
+    halves = []
+    for sl in (slice(0, B // 2), slice(B // 2, B)):
+        xh, ch = cs.unrolled_ista_fwd(g(c), d, g(Y[sl]), g(lam), g(tau), K, every)
+        assert np.array_equal(h(xh), xK[sl])
+        halves.append([h(v) for v in cs.unrolled_ista_bwd(g(c), d, g(Y[sl]), g(lam), g(tau), K, every, ch, g(gx[sl]))])
+    assert rel(halves[0][0] + halves[1][0], gl) <= 1e-5
+    assert rel(halves[0][1] + halves[1][1], gt) <= 1e-5
+    assert np.array_equal(np.concatenate([halves[0][2], halves[1][2]]), gy)
