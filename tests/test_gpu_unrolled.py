@@ -130,8 +130,9 @@ def test_shared_c_batch_shape_forward_and_aggregate_gradients():
     """The differentiable workload's shape (n = 2^16, d = 4, k = 256, K = 50,
     checkpoints every 10) on 4 signals: the forward iterate per signal, and
     the lam / tau gradients, which aggregate over the batch."""
-    n, d, K, every = 1 << 16, 4, 50, 10
+    d, K, every = 4, 50, 10
     c, Xs = workloads.shared_c_batch(batch=4)
+    assert c.shape[0] == 1 << 16
     op = fftref.Operator(c.astype(np.float64), d)
     Y = np.stack([op.A(x.astype(np.float64)) for x in Xs]).astype(np.float32)
     lam0 = 0.01 * np.mean([np.max(np.abs(op.AT(y.astype(np.float64)))) for y in Y])
