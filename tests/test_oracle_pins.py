@@ -509,3 +509,147 @@ def test_deblur_field_shape():
     sig = workloads.deblur_field(side=64)
     assert sig.n == 64 * 64 and sig.d == 2 and sig.k == int(0.1 * sig.n)
     assert np.count_nonzero(sig.x_true) == sig.k and np.all(sig.x_true >= 0)
+
+
+# --------------------------------------------------------------------------
+# Objective (Eq. 3 with the quadratic term halved, alpha read as lam): a
+# hand-worked value, agreement of the three oracle objectives, and planted
+# wrong objectives that must fail.
+# --------------------------------------------------------------------------
+def check_objective_golden(objective_dense):
+    g = _read_golden("objective_n4_d2.txt")
+    A = dense.dense_A(g["c"][0], int(g["d"][0][0]))
+    F = objective_dense(A, g["y"][0], float(g["lam"][0][0]), g["x"][0])
+    assert F == float(g["F"][0][0]), F
+
+
+def test_objective_golden_n4():
+    g = _read_golden("objective_n4_d2.txt")
+    A = dense.dense_A(g["c"][0], int(g["d"][0][0]))
+    r = g["y"][0] - A @ g["x"][0]
+    assert float(r @ r) == float(g["residual_sq"][0][0])
+    assert float(np.abs(g["x"][0]).sum()) == float(g["l1"][0][0])
+    check_objective_golden(dense.objective)
+
+
+def check_objective_agree(objective_fft, n=512, d=4, seed=31):
+    """fftref's objective (residual through the FFT operator) equals the dense
+    one on a random instance with a sparse x, to FP64 rounding."""
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal(n)
+    x = np.where(rng.random(n) < 0.2, rng.standard_normal(n), 0.0)
+    y = rng.standard_normal(n // d)
+    lam = 0.37
+    Fd = dense.objective(dense.dense_A(c, d), y, lam, x)
+    Ff = objective_fft(fftref.Operator(c, d), y, lam, x)
+    assert abs(Ff - Fd) <= 1e-12 * Fd, (Ff, Fd)
+
+
+def test_objective_fft_matches_dense():
+    for n, d in ((512, 4), (256, 2), (1024, 8), (128, 1)):
+        check_objective_agree(fftref.objective, n, d, seed=n + d)
+
+
+def test_objective_2d_matches_dense():
+    from oracle import twod
+    rng = np.random.default_rng(32)
+    s = rng.choice([-1.0, 1.0], size=(16, 16))
+    h = np.zeros((16, 16))
+    h[:3, :3] = rng.random((3, 3))
+    h /= h.sum()
+    x = np.where(rng.random(256) < 0.2, rng.standard_normal(256), 0.0)
+    y = rng.standard_normal(64)
+    lam = 0.21
+    Fd = dense.objective(twod.dense_A2(s, h, 2, 2), y, lam, x)
+    Ft = twod.objective(twod.Operator2D(s, h, 2, 2), y, lam, x)
+    assert abs(Ft - Fd) <= 1e-12 * Fd, (Ft, Fd)
+
+
+def _mut_obj_no_half(A, y, lam, x):
+    r = y - A @ x
+    return float(r @ r) + lam * float(np.abs(x).sum())
+
+
+def _mut_obj_eq3_literal(A, y, lam, x):
+    r = y - A @ x
+    return float(r @ r) + 2.0 * lam * float(np.abs(x).sum())
+
+
+def _mut_obj_no_l1(A, y, lam, x):
+    r = y - A @ x
+    return 0.5 * float(r @ r)
+
+
+def _mut_obj_l2(A, y, lam, x):
+    r = y - A @ x
+    return 0.5 * float(r @ r) + lam * float(np.linalg.norm(x))
+
+
+def _mut_fft_obj_no_half(op, y, lam, x):
+    r = y - op.A(x)
+    return float(r @ r) + lam * float(np.abs(x).sum())
+
+
+def _mut_fft_obj_l2(op, y, lam, x):
+    r = y - op.A(x)
+    return 0.5 * float(r @ r) + lam * float(np.linalg.norm(x))
+
+
+@pytest.mark.parametrize("mut", [_mut_obj_no_half, _mut_obj_eq3_literal, _mut_obj_no_l1, _mut_obj_l2])
+def test_planted_objective_mistakes_fail_golden(mut):
+    with pytest.raises(AssertionError):
+        check_objective_golden(mut)
+
+
+@pytest.mark.parametrize("mut", [_mut_fft_obj_no_half, _mut_fft_obj_l2])
+def test_planted_fft_objective_mistakes_fail_agreement(mut):
+    with pytest.raises(AssertionError):
+        check_objective_agree(mut)
+
+
+# --------------------------------------------------------------------------
+# Batched oracle: the batch is the per-signal Alg. 1, signal by signal.
+# --------------------------------------------------------------------------
+def check_batched_one_by_one(ista_batched):
+    from oracle import batched
+    sigs = [workloads.signal(n, 4, max(1, n // 256), 40 + i) for i, n in enumerate((256, 1024, 512, 8192, 16384))]
+    probs = batched.build_batch(sigs)
+    xs = ista_batched(probs, 30)
+    assert len(xs) == len(probs)
+    for pr, xb in zip(probs, xs):
+        y = pr.y.astype(np.float64)
+        # the plain definition, independently of batched.ista_one's choice
+        # between the dense and the FFT operator
+        A = dense.dense_A(pr.c.astype(np.float64), pr.d)
+        x = np.zeros(pr.n)
+        for _ in range(30):
+            x = dense.soft(x + float(pr.tau) * (A.T @ (y - A @ x)), float(pr.tau) * float(pr.lam))
+        assert _rel(xb, x) < 1e-12
+    # concatenation keeps the order and the per-signal parameters
+    ns, c, yc, lam, tau = batched.concat(probs)
+    assert ns.tolist() == [p.n for p in probs]
+    off = 0
+    for p in probs:
+        np.testing.assert_array_equal(c[off:off + p.n], p.c)
+        off += p.n
+    assert lam.tolist() == [float(p.lam) for p in probs]
+    assert tau.tolist() == [float(p.tau) for p in probs]
+
+
+def test_batched_equals_one_by_one():
+    check_batched_one_by_one(__import__("oracle.batched", fromlist=["ista_batched"]).ista_batched)
+
+
+def _mut_batched_shared_params(problems, iters):
+    from oracle import batched
+    p0 = problems[0]
+    out = []
+    for pr in problems:
+        q = problem.Problem(n=pr.n, d=pr.d, c=pr.c, y=pr.y, x_true=pr.x_true, lam=p0.lam, tau=p0.tau)
+        out.append(batched.ista_one(q, iters))
+    return out
+
+
+def test_planted_batched_mistake_fails():
+    with pytest.raises(AssertionError):
+        check_batched_one_by_one(_mut_batched_shared_params)
