@@ -33,27 +33,41 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_bytes(n, d, ista_iters, admm_iters):
-    """Algorithmic bytes per launch of each solver kernel (float32).
+    """Algorithmic bytes per launch of each solver kernel (float32): the bytes
+    the kernel's schedule must move to or from memory beyond the CU.
 
     Two-launch schedule (per iteration):
       passA (ISTA and ADMM): spectrum Y read + write (8n), c_hat read (4n),
         y_hat read for the m/2 + 1 alias classes (4m);
       passB_ista / passB_admm: Y read + write and the time-domain state
         (x or u) read + write (16n).
-    Persistent schedule (one launch = a whole solve): per iteration Y is
-      read and written by both passes (16n) and c_hat / y_hat are read
-      (4n + 4m); the state stays in registers.  Bytes per launch = iterations
-      x (20n + 4m), plus the state and outputs moved once.
+    Persistent schedule (one launch = a whole solve of T iterations): the
+      row pass reads and writes Y (4n + 4n), and so does the column pass, so
+      16n per iteration, less the first row read of a cold start (Y = 0 is
+      not read) and the last column write (the last iteration ends with the
+      threshold); c_hat (4n) and y_hat (4m, the alias classes' bins) are
+      loaded into registers once per launch and the state stays in
+      registers, written once at the end (ISTA: x, 4n; ADMM: x, z, u, 12n).
     """
     m = n // d
     a = 12 * n + 4 * m
-    per_it = 20 * n + 4 * m
+    once = 4 * n + 4 * m
     return {"passA_ista": a, "passB_ista": 16 * n, "passA_admm": a, "passB_admm": 16 * n,
-            "solve_ista": ista_iters * per_it + 4 * n,
-            "solve_admm": admm_iters * per_it + 12 * n}
+            "solve_ista": (16 * ista_iters - 8) * n + once + 4 * n,
+            "solve_admm": (16 * admm_iters - 8) * n + once + 12 * n}
 
 
-ITER_BYTES_NOTE = "per iteration: 20n + 4m bytes (persistent) or 28n + 4m (two launches)"
+ITER_BYTES_NOTE = ("per iteration: 16n bytes (persistent: Y read and written by the row and the column pass; "
+                   "c_hat and y_hat loaded once per launch, state in registers) or 28n + 4m (two launches)")
+
+
+def progress(msg):
+    """One progress line per benchmark leg on stderr (the JSON line goes to
+    stdout at the end)."""
+    print("[bench %.1fs] %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
+
+
+_T0 = time.perf_counter()
 
 
 def measured_traffic(kernel):
@@ -103,6 +117,7 @@ def main():
     import workloads
 
     dev = torch.device("cuda:0")
+    progress("headline: inputs n=2^22, d=4")
     sig = workloads.large_signal()
     prm = workloads.LARGE_PARAMS
     n, d = sig.n, sig.d
@@ -127,9 +142,11 @@ def main():
         if ev is not None:
             ev[2].record()
 
+    progress("headline: %d warm-up steps" % args.warmup)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    progress("headline: %d timed steps" % args.steps)
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -167,6 +184,7 @@ def main():
     kb = kernel_bytes(n, d, T_ista, T_admm)
 
     if not args.no_roofline:
+        progress("roofline: HIP-event timing of one step, copy kernel")
         cs.timing_enable(True)
         step()
         torch.cuda.synchronize()
@@ -203,14 +221,19 @@ def main():
         }
 
     if not args.no_batched:
+        progress("batched: 512 signals")
         out["batched"] = bench_batched(cs, torch, dev, args.steps, args.warmup)
     if not args.no_2d:
+        progress("2-D: 4096x4096 ADMM")
         out["deblur_2d"] = bench_2d(cs, torch, dev, args.steps, args.warmup, not args.no_cpu_baseline)
     if not args.no_unrolled:
+        progress("unrolled: 64 x 2^16, K=50")
         out["unrolled"] = bench_unrolled(cs, torch, dev, args.steps, args.warmup)
     if not args.no_direct:
+        progress("direct products at n=2^22")
         out["direct_baseline"] = bench_direct(cs, torch, dev, c, d, xs, y)
     if not args.no_deblur1d:
+        progress("deblurring shape: n=2^20, d=2")
         out["deblur_1d"] = bench_deblur1d(cs, torch, dev, args.steps, args.warmup)
 
     if args.copy_mib > 0:
@@ -223,8 +246,10 @@ def main():
                                    "bytes_written": 4 * dst.numel(), "launches": 3}
 
     if not args.no_cpu_baseline:
+        progress("cpu baseline: FP64 oracle sample")
         out["cpu_baseline"] = cpu_baseline(sig, prm, tau, lam)
-    print(json.dumps(out))
+    progress("done")
+    print(json.dumps(out), flush=True)
 
 
 def bench_batched(cs, torch, dev, steps, warmup):
@@ -454,7 +479,8 @@ def bench_unrolled(cs, torch, dev, steps, warmup):
     c = torch.from_numpy(c_np).to(dev)
     xs = torch.from_numpy(xs_np).to(dev)
     Y = torch.stack([cs.circ_apply(c, d, xs[b]) for b in range(B)])
-    lam0 = prm["lam_frac"] * max(cs.circ_apply_T(c, d, Y[b]).abs().max().item() for b in range(B))
+    # lam_t starts at lam_frac times the batch mean of ||A^T y_b||_inf
+    lam0 = prm["lam_frac"] * float(np.mean([cs.circ_apply_T(c, d, Y[b]).abs().max().item() for b in range(B)]))
     tau0 = 1.0 / cs.circ_norm_bound(c).item()
     lam = torch.full((K,), lam0, device=dev)
     tau = torch.full((K,), tau0, device=dev)

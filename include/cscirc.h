@@ -22,10 +22,10 @@
  *     a message (per thread).
  *   - The first call for a given (device, n, d) builds a plan: twiddle tables
  *     (double precision on the host) and a workspace of about 3*n*4 bytes,
- *     allocated with hipMalloc and kept until the process ends.  Calls that
- *     share a plan share its workspace: issue them on one stream (or
- *     serialise them); concurrent calls with the same (n, d) on different
- *     streams race.
+ *     allocated with hipMalloc and kept until the process ends (or the
+ *     caller's block, see cs_set_workspace).  Calls that share a plan share
+ *     its workspace: issue them on one stream (or serialise them);
+ *     concurrent calls with the same (n, d) on different streams race.
  *   - No C++ exception crosses this interface.
  */
 #ifndef CSCIRC_H
@@ -195,6 +195,35 @@ cs_status cs2_ista_solve(const float* s, const float* h, int32_t rows, int32_t c
 cs_status cs2_admm_solve(const float* s, const float* h, int32_t rows, int32_t cols, const float* y, float lambda,
                          float rho, int32_t iters, int32_t warm, float* x, float* z, float* u, float* obj,
                          cs_stream stream);
+
+/* ---- caller-provided workspace -------------------------------------------
+ * The single-signal calls (cs_circ_apply, cs_circ_apply_T, cs_circ_norm_bound,
+ * cs_ista_solve, cs_admm_solve) need, per (n, d), one block of device memory:
+ * the spectrum buffer of the four-step transform (Section 4.2 diagonalises
+ * the circulant with the DFT; the block holds that DFT's intermediate), the
+ * tables of c_hat and of the spectrum of P^T y, the twiddle factors and the
+ * persistent solver's barrier counters and error flag.  By default the
+ * library allocates it on the first call for (device, n, d) and keeps it.
+ *
+ * cs_workspace_bytes: bytes of that block for (n, d); mode 0 (operators),
+ * 1 (ISTA) and 2 (ADMM) share one layout.  Returns 0 for an invalid n, d or
+ * mode.
+ *
+ * cs_set_workspace: from now on the single-signal calls on the current
+ * device use the caller's block `ws` (a DEVICE pointer, 256-byte aligned,
+ * `bytes` long, owned by the caller) instead of library memory: a call whose
+ * (n, d) needs more than `bytes` returns CS_EINVAL and enqueues nothing.  The
+ * library writes the twiddle tables into the block with a kernel on the
+ * call's stream whenever a call's n differs from the previous call's, and
+ * clears the barrier area on the block's first use; the caller must not
+ * modify the block while it is set.  Calls that use one block race unless
+ * they are issued on one stream.  ws == NULL returns to library memory.  An
+ * objective trace (obj != NULL) still takes a small library buffer of
+ * partial sums.  The batched, unrolled and 2-D calls keep their own memory.
+ * Errors: CS_EINVAL (misaligned or too small), CS_ENOTSUP (device index of
+ * 64 or more).  */
+size_t cs_workspace_bytes(int64_t n, int32_t d, int32_t mode);
+cs_status cs_set_workspace(void* ws, size_t bytes);
 
 /* Solver schedule.  For 2^8 <= n <= 2^22 a solve runs as ONE cooperative
  * launch: all iterations in a persistent kernel whose workgroups keep the

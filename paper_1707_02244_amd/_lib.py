@@ -19,7 +19,8 @@ _NAMES = {CS_EINVAL: "CS_EINVAL", CS_ENOMEM: "CS_ENOMEM", CS_EHIP: "CS_EHIP", CS
 EXPORTS = ["cs_circ_apply", "cs_circ_apply_T", "cs_circ_apply_direct", "cs_circ_apply_T_direct", "cs_circ_norm_bound", "cs_ista_solve",
            "cs_admm_solve", "cs_ista_solve_batched", "cs_unrolled_ckpt_bytes", "cs_unrolled_ista_fwd",
            "cs_unrolled_ista_bwd", "cs2_apply", "cs2_apply_T", "cs2_norm_bound", "cs2_ista_solve",
-           "cs2_admm_solve", "cs_set_solver_path", "cs_check_device", "cs_timing_enable",
+           "cs2_admm_solve", "cs_workspace_bytes", "cs_set_workspace", "cs_set_solver_path", "cs_check_device",
+           "cs_timing_enable",
            "cs_timing_read", "cs_last_error", "cs_version"]
 
 
@@ -59,6 +60,8 @@ def load():
         "cs2_norm_bound": [P, P, I32, I32, P, P],
         "cs2_ista_solve": [P, P, I32, I32, P, F, F, I32, P, P, P],
         "cs2_admm_solve": [P, P, I32, I32, P, F, F, I32, I32, P, P, P, P, P],
+        "cs_workspace_bytes": [I64, I32, I32],
+        "cs_set_workspace": [P, ctypes.c_size_t],
         "cs_set_solver_path": [I32],
         "cs_check_device": [P],
         "cs_timing_enable": [I32],
@@ -72,6 +75,7 @@ def load():
         fn.restype = ctypes.c_int
     lib.cs_last_error.restype = ctypes.c_char_p
     lib.cs_unrolled_ckpt_bytes.restype = ctypes.c_size_t
+    lib.cs_workspace_bytes.restype = ctypes.c_size_t
     _lib = lib
     return lib
 
@@ -329,6 +333,24 @@ def _unrolled_function():
             return g_y, g_lam, g_tau, None, None, None, None
 
     return UnrolledISTA
+
+
+def workspace_bytes(n, d, mode=0):
+    """Bytes of the device block a single-signal call of (n, d) needs
+    (mode 0 operators, 1 ISTA, 2 ADMM; one layout); 0 if (n, d) is invalid."""
+    return int(load().cs_workspace_bytes(int(n), int(d), int(mode)))
+
+
+def set_workspace(ws):
+    """Use the caller's device block for the single-signal calls on the
+    current device (ws: a float32 or uint8 CUDA tensor, kept alive by the
+    caller while set), or library memory again (ws None)."""
+    if ws is None:
+        _check(load().cs_set_workspace(None, 0))
+        return
+    if not ws.is_cuda or not ws.is_contiguous():
+        raise ValueError("workspace must be a contiguous GPU tensor")
+    _check(load().cs_set_workspace(ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()))
 
 
 PATH_AUTO, PATH_TWO_PASS, PATH_PERSISTENT = 0, 1, 2

@@ -39,7 +39,18 @@ def _run(cmd):
     return out
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def _stale(src, obj):
+    """An object is stale when it is missing or older than its source, any
+    header under csrc/ or the C ABI header."""
+    if not os.path.exists(obj):
+        return True
+    deps = [src, os.path.join(os.path.dirname(HERE), "include", "cscirc.h")]
+    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    return max(os.path.getmtime(f) for f in deps) > os.path.getmtime(obj)
+
+
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every unit (incremental: only stale objects) and link."""
     os.makedirs(BUILD, exist_ok=True)
     units = []
     for L in ROW_LENGTHS:
@@ -59,8 +70,9 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     units.append((os.path.join(CSRC, "runtime2d.hip"), os.path.join(BUILD, "runtime2d.o"), []))
     units.sort(key=lambda u: ("solve" not in u[1] and "batch" not in u[1], -len(u[1])))
     jobs = jobs or min(16, os.cpu_count() or 4)
+    todo = [u for u in units if not incremental or _stale(u[0], u[1])]
     with cf.ThreadPoolExecutor(jobs) as ex:
-        futs = [ex.submit(_run, [HIPCC] + FLAGS + extra + ["-c", src, "-o", obj]) for src, obj, extra in units]
+        futs = [ex.submit(_run, [HIPCC] + FLAGS + extra + ["-c", src, "-o", obj]) for src, obj, extra in todo]
         for f in futs:
             out = f.result()
             if verbose and out.strip():
@@ -72,4 +84,4 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

@@ -191,27 +191,45 @@ constexpr int kMaxLogNPersistent = 21;
 // 0: choose per size; 1: two launches per iteration; 2: persistent launch
 int g_path = 0;
 
+// Bound of one grid-barrier wait of the persistent solver.  A real wait
+// lasts a few microseconds; a wait that reaches the bound sets the plan's
+// error flag (reported by cs_check_device) and the launch drains.
+constexpr uint64_t kBarWaitMs = 20;
+
+// A plan for (n, d): the four-step geometry and one block of device memory
+// holding, in this order (float2 units, each part rounded up to 64):
+//   barrier area   grid-barrier counters and the error flag (kBarWords words;
+//                  first, so the flag sits at the block's start for every n)
+//   scal           small device scalars
+//   twiddles       W_N1, W_N2, W_N^e (two levels), W_n^k1, W_2N2^p
+//   Y              the four-step spectrum buffer (N complex)
+//   chat, yhat     the c_hat and DFT_n(P^T y) tables (N + 1 complex each)
+// The block is the library's own allocation (cached per device, n, d), a
+// caller's workspace (cs_set_workspace) or the allocation-free entry point's
+// scratch array; `bind` points a plan at it.
 struct Plan {
   int dev = 0;
   int64_t n = 0;
   int d = 0;
   int N = 0, N1 = 0, N2 = 0, M = 0, lo_bits = 0, logN = 0;
   bool persistent[2][5] = {};   // [alg][d/2 index]: cooperative launch fits
-  float2* mem = nullptr;
+  uint64_t bar_ticks = 0;       // bound of one grid-barrier wait (device wall-clock ticks)
+  int64_t oB = 0, oS = 0, oT1 = 0, oT2 = 0, oLo = 0, oHi = 0, oK1 = 0, oP = 0, oY = 0, oC = 0, oYh = 0;
+  size_t bytes = 0;             // size of the memory block
+  float2* mem = nullptr;        // the block (nullptr: not bound)
   unsigned* bar = nullptr;      // grid barrier counters, error flag at [kBarErr]
   float2 *Y = nullptr, *chat = nullptr, *yhat = nullptr;
   float2 *tw1 = nullptr, *tw2 = nullptr, *twlo = nullptr, *twhi = nullptr;
   float2 *twk1 = nullptr, *twp = nullptr;
-  float* scal = nullptr;   // small device scalars (norm bound)
-  double* objbuf = nullptr; // objective-trace partial sums (grown on demand)
-  size_t obj_cap = 0;
-  ~Plan() {
-    if (mem) (void)hipFree(mem);
-    if (objbuf) (void)hipFree(objbuf);
-  }
+  float* scal = nullptr;    // small device scalars (norm bound)
 };
 
-std::map<std::tuple<int, int64_t, int>, std::unique_ptr<Plan>> g_plans;
+// Plans and workspaces live until the process ends and are never destroyed:
+// the caches are heap objects that are never deleted, so no destructor calls
+// into the HIP runtime during static destruction (by then the runtime, or a
+// profiler wrapped around it, may already be finalised).  The device memory is
+// returned with the process.
+auto& g_plans = *new std::map<std::tuple<int, int64_t, int>, std::unique_ptr<Plan>>();
 
 int solve_blocks_per_cu_dispatch(int logN, int alg, int d2) {
   switch (logN) {
@@ -233,6 +251,136 @@ hipError_t launch_solve_dispatch(int logN, int alg, int d2, const SolveArgs& a, 
   }
 }
 
+// Per-device facts the plans need, queried once into fixed arrays (no heap
+// allocation, so the allocation-free entry point can use them): the CU
+// count, the wall-clock rate and whether each persistent-solver instance fits
+// as one cooperative launch.
+constexpr int kMaxDevices = 64;
+struct DevInfo {
+  bool ready = false;
+  int cus = 0;
+  uint64_t bar_ticks = 0;
+  bool persistent[kMaxLogNPersistent + 1][2][4] = {};   // [log2 N][alg][log2 (d/2)]
+};
+DevInfo g_dev[kMaxDevices];
+
+cs_status dev_info(int dev, const DevInfo** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(CS_ENOTSUP, "device %d beyond the supported %d", dev, kMaxDevices);
+  DevInfo& di = g_dev[dev];
+  if (!di.ready) {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
+    // one barrier wait may last at most kBarWaitMs of device wall-clock time
+    di.bar_ticks = uint64_t(khz) * kBarWaitMs;
+    CS_HIP(hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    for (int L = kMinLogNPersistent; L <= kMaxLogNPersistent; ++L) {
+      const int N1 = (L % 2) ? (1 << ((L - 1) / 2)) : (1 << (L / 2 - 1));
+      const int N2 = (1 << L) / N1;
+      for (int alg = 0; alg < 2; ++alg)
+        for (int k = 0; k < 4; ++k) {
+          const int nb = solve_blocks_per_cu_dispatch(L, alg, 1 << k);
+          di.persistent[L][alg][k] = nb >= 1 && int64_t(nb) * di.cus >= N2 / kColsPerBlock;
+        }
+    }
+    di.ready = true;
+  }
+  *out = &di;
+  return CS_OK;
+}
+
+// Geometry and memory layout of the (n, d) plan (no device query).
+void plan_layout(int64_t n, int d, Plan& p) {
+  p.n = n;
+  p.d = d;
+  p.N = int(n / 2);
+  const int pN = ilog2(p.N);
+  p.logN = pN;
+  // four-step split: odd log2 N -> N2 = 2 N1, even -> N2 = 4 N1 (so the
+  // persistent solver's grid N2/8 owns N1/2 row pairs in 2 or 1 per group)
+  p.N1 = (pN % 2) ? (1 << ((pN - 1) / 2)) : (1 << (pN / 2 - 1));
+  p.N2 = p.N / p.N1;
+  p.M = int((n / d) / p.N1);
+  p.lo_bits = (pN + 1) / 2;
+  const int64_t nlo = int64_t(1) << p.lo_bits, nhi = int64_t(p.N) >> p.lo_bits;
+  auto up = [](int64_t v) { return (v + 63) & ~int64_t(63); };
+  p.oB = 0;
+  p.oS = p.oB + up(kBarWords / 2);
+  p.oT1 = p.oS + 64;
+  p.oT2 = p.oT1 + up(p.N1);
+  p.oLo = p.oT2 + up(p.N2);
+  p.oHi = p.oLo + up(nlo);
+  p.oK1 = p.oHi + up(nhi);
+  p.oP = p.oK1 + up(p.N1);
+  p.oY = p.oP + up(p.N2);
+  p.oC = p.oY + up(p.N);
+  p.oYh = p.oC + up(p.N + 1);
+  p.bytes = size_t(p.oYh + up(p.N + 1)) * sizeof(float2);
+}
+
+// Geometry, layout and device facts of the (n, d) plan; binds no memory.
+// Call with g_mu held.
+cs_status plan_geometry(int dev, int64_t n, int d, Plan& p) {
+  const DevInfo* di = nullptr;
+  cs_status st = dev_info(dev, &di);
+  if (st != CS_OK) return st;
+  plan_layout(n, d, p);
+  p.dev = dev;
+  p.bar_ticks = di->bar_ticks;
+  for (int alg = 0; alg < 2; ++alg)
+    for (int k = 0; k < 4; ++k)
+      p.persistent[alg][k] = p.logN >= kMinLogNPersistent && p.logN <= kMaxLogNPersistent &&
+                             di->persistent[p.logN][alg][k];
+  return CS_OK;
+}
+
+void bind(Plan& p, float2* b) {
+  p.mem = b;
+  p.bar = reinterpret_cast<unsigned*>(b + p.oB);
+  p.scal = reinterpret_cast<float*>(b + p.oS);
+  p.tw1 = b + p.oT1; p.tw2 = b + p.oT2; p.twlo = b + p.oLo; p.twhi = b + p.oHi;
+  p.twk1 = b + p.oK1; p.twp = b + p.oP;
+  p.Y = b + p.oY; p.chat = b + p.oC; p.yhat = b + p.oYh;
+}
+
+// Twiddle tables of a plan computed on the device (double precision, rounded
+// to float), for memory the library does not fill from the host.
+__global__ void k_twiddles(float2* __restrict__ tw1, float2* __restrict__ tw2, float2* __restrict__ twlo,
+                           float2* __restrict__ twhi, float2* __restrict__ twk1, float2* __restrict__ twp,
+                           int N1, int N2, int lo_bits, int64_t N, int64_t n) {
+  const int64_t nlo = int64_t(1) << lo_bits, nhi = N >> lo_bits;
+  auto rt = [](int64_t e, int64_t L) {
+    double s_, c_;
+    sincos(-2.0 * M_PI * double(e % L) / double(L), &s_, &c_);
+    return make_float2(float(c_), float(s_));
+  };
+  const int64_t total = int64_t(N1) + N2 + nlo + nhi + N1 + N2;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+    int64_t k = i;
+    if (k < N1) { tw1[k] = rt(k, N1); continue; }
+    k -= N1;
+    if (k < N2) { tw2[k] = rt(k, N2); continue; }
+    k -= N2;
+    if (k < nlo) { twlo[k] = rt(k, N); continue; }
+    k -= nlo;
+    if (k < nhi) { twhi[k] = rt(k * nlo, N); continue; }
+    k -= nhi;
+    if (k < N1) { twk1[k] = rt(k, n); continue; }
+    k -= N1;
+    twp[k] = rt(k, 2 * int64_t(N2));
+  }
+}
+
+cs_status device_twiddles(const Plan& p, hipStream_t s) {
+  const int64_t total = int64_t(p.N1) * 2 + int64_t(p.N2) * 2 + (int64_t(1) << p.lo_bits) + (int64_t(p.N) >> p.lo_bits);
+  const unsigned blocks = unsigned(std::min<int64_t>((total + 255) / 256, 1024));
+  k_twiddles<<<dim3(blocks), dim3(256), 0, s>>>(p.tw1, p.tw2, p.twlo, p.twhi, p.twk1, p.twp, p.N1, p.N2,
+                                                p.lo_bits, int64_t(p.N), p.n);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
+}
+
+// The library's own plan for (current device, n, d), allocated and filled
+// on first use and cached.
 cs_status get_plan(int64_t n, int d, Plan** out) {
   int dev = 0;
   CS_HIP(hipGetDevice(&dev));
@@ -244,60 +392,89 @@ cs_status get_plan(int64_t n, int d, Plan** out) {
     return CS_OK;
   }
   auto p = std::make_unique<Plan>();
-  p->dev = dev;
-  p->n = n;
-  p->d = d;
-  p->N = int(n / 2);
-  const int pN = ilog2(p->N);
-  p->logN = pN;
-  // four-step split: odd log2 N -> N2 = 2 N1, even -> N2 = 4 N1 (so the
-  // persistent solver's grid N2/8 owns N1/2 row pairs in 2 or 1 per group)
-  p->N1 = (pN % 2) ? (1 << ((pN - 1) / 2)) : (1 << (pN / 2 - 1));
-  p->N2 = p->N / p->N1;
-  p->M = int((n / d) / p->N1);
-  p->lo_bits = (pN + 1) / 2;
+  cs_status st = plan_geometry(dev, n, d, *p);
+  if (st != CS_OK) return st;
+  float2* b = nullptr;
+  hipError_t e = hipMalloc(&b, p->bytes);
+  if (e != hipSuccess) return fail(CS_ENOMEM, "hipMalloc of %zu bytes for plan n=%lld d=%d failed: %s",
+                                   p->bytes, (long long)n, d, hipGetErrorString(e));
+  bind(*p, b);
+  // barrier area, scalars and twiddle tables from the host (zeros for the
+  // first two)
   const int64_t nlo = int64_t(1) << p->lo_bits, nhi = int64_t(p->N) >> p->lo_bits;
-  // layout (float2 elements, each block rounded up to 64)
-  auto up = [](int64_t v) { return (v + 63) & ~int64_t(63); };
-  const int64_t oY = 0, oC = oY + up(p->N), oYh = oC + up(p->N + 1), oT1 = oYh + up(p->N + 1);
-  const int64_t oT2 = oT1 + up(p->N1), oLo = oT2 + up(p->N2), oHi = oLo + up(nlo);
-  const int64_t oK1 = oHi + up(nhi), oP = oK1 + up(p->N1), oS = oP + up(p->N2);
-  const int64_t oB = oS + 64;   // barrier area: kBarWords unsigned
-  const int64_t total = oB + up(kBarWords / 2);
-  hipError_t e = hipMalloc(&p->mem, size_t(total) * sizeof(float2));
-  if (e != hipSuccess) return fail(CS_ENOMEM, "hipMalloc of %lld bytes for plan n=%lld d=%d failed: %s",
-                                   (long long)(total * sizeof(float2)), (long long)n, d, hipGetErrorString(e));
-  float2* b = p->mem;
-  p->Y = b + oY; p->chat = b + oC; p->yhat = b + oYh;
-  p->tw1 = b + oT1; p->tw2 = b + oT2; p->twlo = b + oLo; p->twhi = b + oHi;
-  p->twk1 = b + oK1; p->twp = b + oP; p->scal = reinterpret_cast<float*>(b + oS);
-  p->bar = reinterpret_cast<unsigned*>(b + oB);
-  e = hipMemset(p->bar, 0, kBarWords * sizeof(unsigned));
-  if (e != hipSuccess) return fail(CS_EHIP, "hipMemset of plan flags failed: %s", hipGetErrorString(e));
-  if (pN >= kMinLogNPersistent && pN <= kMaxLogNPersistent) {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
-      for (int alg = 0; alg < 2; ++alg)
-        for (int d2 : {1, 2, 4, 8}) {
-          const int nb = solve_blocks_per_cu_dispatch(pN, alg, d2);
-          p->persistent[alg][ilog2(d2)] = nb >= 1 && int64_t(nb) * cus >= p->N2 / kColsPerBlock;
-        }
-    }
-  }
-  std::vector<float2> h(size_t(total - oT1));
+  std::vector<float2> h(size_t(p->oY), make_float2(0.f, 0.f));
   auto put = [&](int64_t off, int64_t cnt, auto fn) {
-    for (int64_t i = 0; i < cnt; ++i) h[size_t(off - oT1 + i)] = fn(i);
+    for (int64_t i = 0; i < cnt; ++i) h[size_t(off + i)] = fn(i);
   };
-  put(oT1, p->N1, [&](int64_t i) { return root(i, p->N1); });
-  put(oT2, p->N2, [&](int64_t i) { return root(i, p->N2); });
-  put(oLo, nlo, [&](int64_t i) { return root(i, p->N); });
-  put(oHi, nhi, [&](int64_t i) { return root(i * nlo, p->N); });
-  put(oK1, p->N1, [&](int64_t i) { return root(i, n); });
-  put(oP, p->N2, [&](int64_t i) { return root(i, 2 * int64_t(p->N2)); });
-  e = hipMemcpy(b + oT1, h.data(), h.size() * sizeof(float2), hipMemcpyHostToDevice);
+  put(p->oT1, p->N1, [&](int64_t i) { return root(i, p->N1); });
+  put(p->oT2, p->N2, [&](int64_t i) { return root(i, p->N2); });
+  put(p->oLo, nlo, [&](int64_t i) { return root(i, p->N); });
+  put(p->oHi, nhi, [&](int64_t i) { return root(i * nlo, p->N); });
+  put(p->oK1, p->N1, [&](int64_t i) { return root(i, n); });
+  put(p->oP, p->N2, [&](int64_t i) { return root(i, 2 * int64_t(p->N2)); });
+  e = hipMemcpy(b, h.data(), h.size() * sizeof(float2), hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(CS_EHIP, "hipMemcpy of plan tables failed: %s", hipGetErrorString(e));
   *out = p.get();
   g_plans[key] = std::move(p);
+  return CS_OK;
+}
+
+// Memory blocks the caller provides: a workspace set by cs_set_workspace per
+// device, and the allocation-free entry point's scratch array.  `tables_n` is
+// the n whose twiddle tables the block holds (0: none yet); a block whose
+// barrier area has not been cleared yet has `cleared` false.
+struct ExtBlock {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  int64_t tables_n = 0;
+  bool cleared = false;
+};
+ExtBlock g_ws[kMaxDevices];
+
+// A plan for (n, d) bound to an external block: geometry from plan_geometry,
+// twiddle tables computed on the stream when the block holds another n's,
+// barrier area (counters and error flag) cleared on the block's first use.
+// Call with g_mu held.
+cs_status bind_external(int dev, int64_t n, int d, ExtBlock& blk, hipStream_t s, Plan& p) {
+  cs_status st = plan_geometry(dev, n, d, p);
+  if (st != CS_OK) return st;
+  if (p.bytes > blk.bytes)
+    return fail(CS_EINVAL, "workspace of %zu bytes is too small for n=%lld d=%d (needs %zu bytes)", blk.bytes,
+                (long long)n, d, p.bytes);
+  bind(p, static_cast<float2*>(blk.ptr));
+  if (!blk.cleared) {
+    if ((st = fill(reinterpret_cast<float*>(p.bar), kBarWords, 0.0f, s)) != CS_OK) return st;
+    blk.cleared = true;
+  }
+  if (blk.tables_n != n) {
+    if ((st = device_twiddles(p, s)) != CS_OK) return st;
+    blk.tables_n = n;
+  }
+  return CS_OK;
+}
+
+// The plan a single-signal call runs on: bound to the device's workspace if
+// the caller has set one, else the library's cached plan.  `cached` (may be
+// null) receives the library plan when one is used (it owns the objective
+// buffer).
+// The external blocks of a device whose error flags cs_check_device reads.
+std::vector<ExtBlock*> ext_blocks(int dev) { return {&g_ws[dev]}; }
+
+cs_status plan_for_call(int64_t n, int d, hipStream_t s, Plan& view, Plan** cached) {
+  int dev = 0;
+  CS_HIP(hipGetDevice(&dev));
+  if (dev >= 0 && dev < kMaxDevices) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_ws[dev].ptr) {
+      if (cached) *cached = nullptr;
+      return bind_external(dev, n, d, g_ws[dev], s, view);
+    }
+  }
+  Plan* P = nullptr;
+  cs_status st = get_plan(n, d, &P);
+  if (st != CS_OK) return st;
+  view = *P;
+  if (cached) *cached = P;
   return CS_OK;
 }
 
@@ -414,6 +591,7 @@ SolveArgs solve_args(const Plan& P) {
   a.tw1 = P.tw1; a.tw2 = P.tw2; a.twlo = P.twlo; a.twhi = P.twhi; a.twk1 = P.twk1; a.twp = P.twp;
   a.lo_bits = P.lo_bits;
   a.bar = P.bar; a.err = reinterpret_cast<int*>(P.bar + kBarErr);
+  a.max_ticks = P.bar_ticks;
   a.inv_n = float(1.0 / double(P.n));
   a.inv_d = float(1.0 / double(P.d));
   return a;
@@ -477,7 +655,7 @@ __global__ void k_group_scatter(const GItem* __restrict__ items, int64_t n, cons
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
     x[o + i] = xg[s * n + i];
 }
-std::map<int, BatchState> g_batch;
+auto& g_batch = *new std::map<int, BatchState>();
 
 hipError_t launch_batch_dispatch(int d2, const BatchSig* sigs, int count, unsigned* queue, int iters,
                                  int grid, hipStream_t s) {
@@ -537,23 +715,32 @@ __global__ void k_unrolled_grads(const double* __restrict__ part, int count, con
 }
 
 // Partial-sum buffers of an objective trace over `iters` iterations:
-// res[iters][N1/2] (one per row-pass workgroup), then l1[iters][N2/8].
-cs_status get_objbuf(Plan& P, int iters, double** res, double** l1, hipStream_t s) {
+// res[iters][N1/2] (one per row-pass workgroup), then l1[iters][N2/8].  One
+// grow-only buffer per device, shared by traced solves on that device.
+struct ObjBuf {
+  double* p = nullptr;
+  size_t cap = 0;
+};
+ObjBuf g_obj[kMaxDevices];
+
+cs_status get_objbuf(const Plan& P, int iters, double** res, double** l1, hipStream_t s) {
   const size_t nres = size_t(P.N1 / 2), nl1 = size_t(P.N2 / kColsPerBlock);
   const size_t need = size_t(iters) * (nres + nl1);
+  if (P.dev < 0 || P.dev >= kMaxDevices) return fail(CS_ENOTSUP, "device %d beyond the supported range", P.dev);
   std::lock_guard<std::mutex> lk(g_mu);
-  if (P.obj_cap < need) {
+  ObjBuf& B = g_obj[P.dev];
+  if (B.cap < need) {
     CS_HIP(hipStreamSynchronize(s));
-    if (P.objbuf) CS_HIP(hipFree(P.objbuf));
-    P.objbuf = nullptr;
-    P.obj_cap = 0;
-    hipError_t e = hipMalloc(&P.objbuf, need * sizeof(double));
+    if (B.p) CS_HIP(hipFree(B.p));
+    B.p = nullptr;
+    B.cap = 0;
+    hipError_t e = hipMalloc(&B.p, need * sizeof(double));
     if (e != hipSuccess) return fail(CS_ENOMEM, "hipMalloc of %zu bytes for the objective trace failed",
                                      need * sizeof(double));
-    P.obj_cap = need;
+    B.cap = need;
   }
-  *res = P.objbuf;
-  *l1 = P.objbuf + size_t(iters) * nres;
+  *res = B.p;
+  *l1 = B.p + size_t(iters) * nres;
   return CS_OK;
 }
 
@@ -567,7 +754,7 @@ struct UPlan {
   size_t part_cap = 0;
   void* mem = nullptr;
 };
-std::map<std::tuple<int, int64_t, int, int, int>, std::unique_ptr<UPlan>> g_uplans;
+auto& g_uplans = *new std::map<std::tuple<int, int64_t, int, int, int>, std::unique_ptr<UPlan>>();
 
 int64_t ckpt_count(int K, int every) { return K > 0 ? (K - 1) / every : 0; }
 
@@ -615,6 +802,77 @@ cs_status check_unrolled(const float* c, int64_t n, int d, int Bt, const float* 
   if (Bt < 1 || Bt > 65535) return fail(CS_EINVAL, "batch=%d must be in [1, 65535]", Bt);
   if (K < 1) return fail(CS_EINVAL, "K=%d must be >= 1", K);
   if (every < 1) return fail(CS_EINVAL, "every=%d must be >= 1", every);
+  return CS_OK;
+}
+
+cs_status check_ista(const float* c, int64_t n, int d, const float* y, float lambda, float tau, int iters,
+                     const float* x) {
+  cs_status st = check_common(c, n, d);
+  if (st != CS_OK) return st;
+  if (!y || !x) return fail(CS_EINVAL, "y or x is NULL");
+  if (!finite(lambda) || lambda < 0.0f) return fail(CS_EINVAL, "lambda=%g must be finite and >= 0", lambda);
+  if (!finite(tau) || tau <= 0.0f) return fail(CS_EINVAL, "tau=%g must be finite and > 0", tau);
+  if (iters < 0) return fail(CS_EINVAL, "iters=%d must be >= 0", iters);
+  return CS_OK;
+}
+
+// Launch with per-launch timing when `timing` (diagnostics) is allowed.
+template <class F>
+hipError_t maybe_timed(bool timing, int kind, hipStream_t s, F&& launch) {
+  return timing ? timed(kind, s, launch) : launch();
+}
+
+// ISTA (Alg. 1) on the plan V for iters >= 1: the c_hat / y_hat tables, then
+// one persistent launch or two launches per iteration (always two with an
+// objective trace).  `timing`: the launches may be bracketed by the timing
+// events (which the library creates on first use).
+cs_status ista_run(const Plan& V, const float* c, const float* y, float lambda, float tau, int iters, float* x,
+                   float* obj, hipStream_t s, bool timing) {
+  const Plan* P = &V;
+  const int64_t n = V.n;
+  const int d = V.d;
+  cs_status st = CS_OK;
+  if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
+  if ((st = setup_yhat(*P, y, s)) != CS_OK) return st;
+  bool pers = false;
+  if (!obj && (st = use_persistent(*P, 0, &pers)) != CS_OK) return st;
+  if (pers) {
+    // barrier counters start at zero (bit pattern of 0.0f); the error flag is
+    // cleared by cs_check_device
+    if ((st = fill(reinterpret_cast<float*>(P->bar), kBarErr, 0.0f, s)) != CS_OK) return st;
+    SolveArgs sa = solve_args(*P);
+    sa.x = x;
+    sa.iters = iters;
+    sa.tau = tau;
+    sa.thr = tau * lambda;
+    CS_LAUNCH(maybe_timed(timing, T_S_ISTA, s, [&] { return launch_solve_dispatch(P->logN, 0, d / 2, sa, s); }));
+    return CS_OK;
+  }
+  if ((st = fill(reinterpret_cast<float*>(P->Y), size_t(P->N) * 2, 0.0f, s)) != CS_OK) return st;
+  if ((st = fill(x, size_t(n), 0.0f, s)) != CS_OK) return st;
+  double *res = nullptr, *l1 = nullptr;
+  if (obj && (st = get_objbuf(*P, iters, &res, &l1, s)) != CS_OK) return st;
+  const int nres = P->N1 / 2, nl1 = P->N2 / kColsPerBlock;
+  PassAArgs a = argsA(*P);
+  a.tau = tau;
+  PassBArgs b = argsB(*P);
+  b.thr = tau * lambda;
+  b.u = x;
+  // objective trace: obj[t-1] = F(x(t)); the row pass of iteration t + 1
+  // sees x(t)'s spectrum, and one residual-only row pass follows the loop
+  for (int t = 1; t <= iters; ++t) {
+    a.res = (obj && t >= 2) ? res + size_t(t - 2) * nres : nullptr;
+    CS_LAUNCH(maybe_timed(timing, T_A_ISTA, s, [&] { return launchA(*P, A_ISTA, a, s); }));
+    b.last = (t == iters) && !obj;
+    b.l1 = obj ? l1 + size_t(t - 1) * nl1 : nullptr;
+    CS_LAUNCH(maybe_timed(timing, T_B_ISTA, s, [&] { return launchB(*P, B_ISTA, b, s); }));
+  }
+  if (obj) {
+    a.res = res + size_t(iters - 1) * nres;
+    CS_LAUNCH(launchA(*P, A_RES, a, s));
+    if ((st = objective_reduce(res, nres, l1, nl1, 0.5 / double(n / d), double(lambda), obj, iters, s)) != CS_OK)
+      return st;
+  }
   return CS_OK;
 }
 
@@ -1024,6 +1282,33 @@ cs_status cs_unrolled_ista_bwd(const float* c, int64_t n, int32_t d, int32_t Bt,
   return CS_OK;
 }
 
+size_t cs_workspace_bytes(int64_t n, int32_t d, int32_t mode) {
+  if (mode < 0 || mode > 2) return 0;
+  if (!is_pow2(n) || n < kMinN || n > kMaxN || (d != 2 && d != 4 && d != 8 && d != 16)) return 0;
+  Plan p;
+  plan_layout(n, d, p);
+  return p.bytes;
+}
+
+cs_status cs_set_workspace(void* ws, size_t bytes) {
+  if (ws && (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(CS_EINVAL, "workspace %p must be 256-byte aligned", ws);
+  if (ws && bytes < cs_workspace_bytes(kMinN, 16, 0))
+    return fail(CS_EINVAL, "workspace of %zu bytes is below the smallest plan (%zu bytes)", bytes,
+                cs_workspace_bytes(kMinN, 16, 0));
+  int dev = 0;
+  CS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CS_ENOTSUP, "device %d beyond the supported %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_mu);
+  ExtBlock& b = g_ws[dev];
+  b.ptr = ws;
+  b.bytes = ws ? bytes : 0;
+  b.tables_n = 0;
+  b.cleared = false;
+  g_err.clear();
+  return CS_OK;
+}
+
 cs_status cs_set_solver_path(int32_t path) {
   if (path < 0 || path > 2) return fail(CS_EINVAL, "path=%d must be 0, 1 or 2", path);
   std::lock_guard<std::mutex> lk(g_mu);
@@ -1038,16 +1323,29 @@ cs_status cs_check_device(cs_stream stream) {
   int dev = 0;
   CS_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_mu);
+  // the error flag of one block: read, and cleared if set
+  auto check = [&](unsigned* bar, const char* what) -> cs_status {
+    unsigned flag = 0;
+    CS_HIP(hipMemcpy(&flag, bar + kBarErr, sizeof flag, hipMemcpyDeviceToHost));
+    if (flag) {
+      const unsigned zero = 0;
+      CS_HIP(hipMemcpy(bar + kBarErr, &zero, sizeof zero, hipMemcpyHostToDevice));
+      return fail(CS_EHIP, "a grid barrier wait exceeded its bound (%s)", what);
+    }
+    return CS_OK;
+  };
+  cs_status st = CS_OK;
   for (auto& kv : g_plans) {
     Plan& P = *kv.second;
     if (P.dev != dev) continue;
-    unsigned flag = 0;
-    CS_HIP(hipMemcpy(&flag, P.bar + kBarErr, sizeof flag, hipMemcpyDeviceToHost));
-    if (flag) {
-      const unsigned zero = 0;
-      CS_HIP(hipMemcpy(P.bar + kBarErr, &zero, sizeof zero, hipMemcpyHostToDevice));
-      return fail(CS_EHIP, "a grid barrier wait exceeded its bound (n=%lld d=%d)", (long long)P.n, P.d);
-    }
+    char what[64];
+    snprintf(what, sizeof what, "n=%lld d=%d", (long long)P.n, P.d);
+    if ((st = check(P.bar, what)) != CS_OK) return st;
+  }
+  if (dev >= 0 && dev < kMaxDevices) {
+    for (ExtBlock* b : ext_blocks(dev))
+      if (b->ptr && b->cleared && (st = check(static_cast<unsigned*>(b->ptr), "caller-provided memory")) != CS_OK)
+        return st;
   }
   g_err.clear();
   return CS_OK;
@@ -1097,9 +1395,10 @@ cs_status cs_circ_apply(const float* c, int64_t n, int32_t d, const float* x, fl
   cs_status st = check_common(c, n, d);
   if (st != CS_OK) return st;
   if (!x || !y) return fail(CS_EINVAL, "x or y is NULL");
-  Plan* P = nullptr;
-  if ((st = get_plan(n, d, &P)) != CS_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Plan V;
+  if ((st = plan_for_call(n, d, s, V, nullptr)) != CS_OK) return st;
+  const Plan* P = &V;
   if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
   PassBArgs b = argsB(*P);
   b.in0 = x;
@@ -1117,9 +1416,10 @@ cs_status cs_circ_apply_T(const float* c, int64_t n, int32_t d, const float* r, 
   cs_status st = check_common(c, n, d);
   if (st != CS_OK) return st;
   if (!r || !x) return fail(CS_EINVAL, "r or x is NULL");
-  Plan* P = nullptr;
-  if ((st = get_plan(n, d, &P)) != CS_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Plan V;
+  if ((st = plan_for_call(n, d, s, V, nullptr)) != CS_OK) return st;
+  const Plan* P = &V;
   if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
   PassBArgs b = argsB(*P);
   b.in0 = r;
@@ -1158,9 +1458,10 @@ cs_status cs_circ_norm_bound(const float* c, int64_t n, float* out, cs_stream st
   cs_status st = check_common(c, n, 2);
   if (st != CS_OK) return st;
   if (!out) return fail(CS_EINVAL, "out is NULL");
-  Plan* P = nullptr;
-  if ((st = get_plan(n, 2, &P)) != CS_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Plan V;
+  if ((st = plan_for_call(n, 2, s, V, nullptr)) != CS_OK) return st;
+  const Plan* P = &V;
   if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
   if ((st = fill(out, 1, 0.0f, s)) != CS_OK) return st;
   if ((st = max_abs2(P->chat, P->N + 1, out, s)) != CS_OK) return st;
@@ -1170,62 +1471,17 @@ cs_status cs_circ_norm_bound(const float* c, int64_t n, float* out, cs_stream st
 
 cs_status cs_ista_solve(const float* c, int64_t n, int32_t d, const float* y, float lambda,
                         float tau, int32_t iters, float* x, float* obj, cs_stream stream) {
-  cs_status st = check_common(c, n, d);
+  cs_status st = check_ista(c, n, d, y, lambda, tau, iters, x);
   if (st != CS_OK) return st;
-  if (!y || !x) return fail(CS_EINVAL, "y or x is NULL");
-  if (!finite(lambda) || lambda < 0.0f) return fail(CS_EINVAL, "lambda=%g must be finite and >= 0", lambda);
-  if (!finite(tau) || tau <= 0.0f) return fail(CS_EINVAL, "tau=%g must be finite and > 0", tau);
-  if (iters < 0) return fail(CS_EINVAL, "iters=%d must be >= 0", iters);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (iters == 0) {
     if ((st = fill(x, size_t(n), 0.0f, s)) != CS_OK) return st;
     g_err.clear();
     return CS_OK;
   }
-  Plan* P = nullptr;
-  if ((st = get_plan(n, d, &P)) != CS_OK) return st;
-  if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
-  if ((st = setup_yhat(*P, y, s)) != CS_OK) return st;
-  bool pers = false;
-  if (!obj && (st = use_persistent(*P, 0, &pers)) != CS_OK) return st;
-  if (pers) {
-    // barrier counters start at zero (bit pattern of 0.0f); the error flag is
-    // cleared by cs_check_device
-    if ((st = fill(reinterpret_cast<float*>(P->bar), kBarErr, 0.0f, s)) != CS_OK) return st;
-    SolveArgs sa = solve_args(*P);
-    sa.x = x;
-    sa.iters = iters;
-    sa.tau = tau;
-    sa.thr = tau * lambda;
-    CS_LAUNCH(timed(T_S_ISTA, s, [&] { return launch_solve_dispatch(P->logN, 0, d / 2, sa, s); }));
-    g_err.clear();
-    return CS_OK;
-  }
-  if ((st = fill(reinterpret_cast<float*>(P->Y), size_t(P->N) * 2, 0.0f, s)) != CS_OK) return st;
-  if ((st = fill(x, size_t(n), 0.0f, s)) != CS_OK) return st;
-  double *res = nullptr, *l1 = nullptr;
-  if (obj && (st = get_objbuf(*P, iters, &res, &l1, s)) != CS_OK) return st;
-  const int nres = P->N1 / 2, nl1 = P->N2 / kColsPerBlock;
-  PassAArgs a = argsA(*P);
-  a.tau = tau;
-  PassBArgs b = argsB(*P);
-  b.thr = tau * lambda;
-  b.u = x;
-  // objective trace: obj[t-1] = F(x(t)); the row pass of iteration t + 1
-  // sees x(t)'s spectrum, and one residual-only row pass follows the loop
-  for (int t = 1; t <= iters; ++t) {
-    a.res = (obj && t >= 2) ? res + size_t(t - 2) * nres : nullptr;
-    CS_LAUNCH(timed(T_A_ISTA, s, [&] { return launchA(*P, A_ISTA, a, s); }));
-    b.last = (t == iters) && !obj;
-    b.l1 = obj ? l1 + size_t(t - 1) * nl1 : nullptr;
-    CS_LAUNCH(timed(T_B_ISTA, s, [&] { return launchB(*P, B_ISTA, b, s); }));
-  }
-  if (obj) {
-    a.res = res + size_t(iters - 1) * nres;
-    CS_LAUNCH(launchA(*P, A_RES, a, s));
-    if ((st = objective_reduce(res, nres, l1, nl1, 0.5 / double(n / d), double(lambda), obj, iters, s)) != CS_OK)
-      return st;
-  }
+  Plan V;
+  if ((st = plan_for_call(n, d, s, V, nullptr)) != CS_OK) return st;
+  if ((st = ista_run(V, c, y, lambda, tau, iters, x, obj, s, true)) != CS_OK) return st;
   g_err.clear();
   return CS_OK;
 }
@@ -1249,8 +1505,9 @@ cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, fl
     g_err.clear();
     return CS_OK;
   }
-  Plan* P = nullptr;
-  if ((st = get_plan(n, d, &P)) != CS_OK) return st;
+  Plan V;
+  if ((st = plan_for_call(n, d, s, V, nullptr)) != CS_OK) return st;
+  const Plan* P = &V;
   if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
   if ((st = setup_yhat(*P, y, s)) != CS_OK) return st;
   bool pers = false;

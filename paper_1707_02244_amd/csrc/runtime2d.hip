@@ -35,17 +35,15 @@ struct Plan2D {
   float2 *twR = nullptr, *twH = nullptr, *twc = nullptr;
   double* objbuf = nullptr;
   size_t obj_cap = 0;
-  ~Plan2D() {
-    if (mem) (void)hipFree(mem);
-    if (objbuf) (void)hipFree(objbuf);
-  }
   size_t g_count() const { return size_t(H / 2 + 1) * 2 * size_t(R); }
   size_t y_count() const { return size_t(H / 2 + 1) * size_t(R / 2); }
   int col_grid() const { return H / 2; }
   int row_grid() const { return R / kRows2; }
 };
 
-std::map<std::tuple<int, int, int>, std::unique_ptr<Plan2D>> g_plans2;
+// Never destroyed (see the 1-D plan cache): no HIP call during static
+// destruction; the device memory is returned with the process.
+auto& g_plans2 = *new std::map<std::tuple<int, int, int>, std::unique_ptr<Plan2D>>();
 
 cs_status get_plan2(int R, int C, Plan2D** out) {
   int dev = 0;

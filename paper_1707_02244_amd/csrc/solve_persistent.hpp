@@ -27,8 +27,9 @@
 // Grid size G = N2 / CB; the split is chosen so that N1/2 = AI * G with AI = 1
 // or 2.  The launch is cooperative (hipLaunchCooperativeKernel), so all G
 // workgroups are resident and the barrier's wait always ends; the wait is also
-// bounded (kSpinLimit polls): hitting the bound sets an error flag, and every
-// later wait returns at once, so a faulty launch still drains.
+// bounded in time (the device wall clock, max_ticks per wait): hitting the
+// bound sets an error flag, and every later wait returns at once, so a faulty
+// launch still drains within about one bound.
 #pragma once
 #include <stdint.h>
 
@@ -62,7 +63,6 @@ __device__ __forceinline__ void static_for(F&& f) {
     static_for<B + 1, E>(f);
   }
 }
-constexpr unsigned kSpinLimit = 1u << 20;   // polls (~40 ms); a real wait is ~100 us
 
 struct SolveArgs {
   float2* Y;               // [N1][N2] spectrum exchange buffer
@@ -80,6 +80,7 @@ struct SolveArgs {
   float* u;                // ADMM: in (warm) / out u(T)
   unsigned* bar;           // grid barrier counters (kBarWords words), zero at launch
   int* err;                // set to 1 if a barrier wait hit its bound
+  uint64_t max_ticks;      // bound of one barrier wait in wall-clock ticks
   int iters;
   int warm;
   float tau;               // ISTA step
@@ -206,8 +207,8 @@ __device__ __forceinline__ void class_step(float2 (&A)[8], float2 (&Bv)[8], cons
 // completed, the workgroup synchronises, lane 0 of wave 0 arrives, and wave 0
 // polls all counters at once (lane c reads counter c) until every one has
 // reached its target; a workgroup barrier releases the other waves.  The wait
-// is bounded; hitting the bound sets the error flag, and a set flag ends every
-// later wait at once.
+// is bounded in wall-clock time; hitting the bound sets the error flag, and
+// every poll also reads the flag, so a set flag ends every later wait at once.
 #ifndef CS_BAR_COUNTERS
 #define CS_BAR_COUNTERS 256
 #endif
@@ -220,7 +221,7 @@ constexpr int kBarErr = kBarCounters * kBarStride;    // error flag, its own lin
 constexpr int kBarWords = kBarErr + kBarStride;       // size of the barrier area
 
 template <int NC>
-__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned target, int* err) {
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned target, int* err, uint64_t max_ticks) {
   static_assert(NC >= 1 && NC <= kBarCounters, "");
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
@@ -228,7 +229,7 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned target, int
     const unsigned lane = threadIdx.x;
     if (lane == 0)
       __hip_atomic_fetch_add(bar + (blockIdx.x % NC) * kBarStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned spins = 0;
+    const uint64_t t0 = wall_clock64();
     while (true) {
       bool ok = true;
 #pragma unroll
@@ -238,12 +239,13 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned target, int
         ok &= r;
       }
       if (__all(ok)) break;
-      __builtin_amdgcn_s_sleep(CS_BAR_SLEEP);
-      if (++spins > kSpinLimit) {
+      // a set flag (an earlier wait of this launch expired) ends the wait at once
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+      if (wall_clock64() - t0 > max_ticks) {
         if (lane == 0) __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
-      if ((spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+      __builtin_amdgcn_s_sleep(CS_BAR_SLEEP);
     }
   }
   __syncthreads();
@@ -511,7 +513,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
         }
       }
       col_forward(A, B);
-      grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err);
+      grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err, a.max_ticks);
     }
     __syncthreads();
 
@@ -583,7 +585,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
 #pragma unroll
         for (int r = 0; r < 8; ++r) st_coh_pair(rs, row_elem(r), va[r], vb[r]);
       }
-      grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err);
+      grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err, a.max_ticks);
 
       // ---- column pass -------------------------------------------------------
       float2 A[8], B[8];
@@ -630,7 +632,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
       }
       if (!last) {
         col_forward(A, B);
-        grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err);
+        grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err, a.max_ticks);
       }
     }
 
@@ -721,7 +723,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
     }
     __syncthreads();
     col_forward_store();
-    grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err);
+    grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err, a.max_ticks);
   }
   __syncthreads();
 
@@ -848,7 +850,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
                lds[lpr((2 * (i / (2 * N2)) + (i & 1)) * LDA + (i % (2 * N2)) / 2)]);
       }
     }
-    grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err);
+    grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err, a.max_ticks);
 
     // ---- column pass: inverse columns, epilogue, forward columns -----------
     {
@@ -899,7 +901,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
     if (!last) {
       __syncthreads();
       col_forward_store();
-      grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err);
+      grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err, a.max_ticks);
     }
   }
 

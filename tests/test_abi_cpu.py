@@ -134,3 +134,37 @@ def test_direct_products_reject_null_pointers():
     assert lib.cs_circ_apply_direct(FAKE, 4096, 4, FAKE, NULL, NULL) == _lib.CS_EINVAL
     assert lib.cs_circ_apply_T_direct(FAKE, 4096, 4, NULL, FAKE, NULL) == _lib.CS_EINVAL
     assert lib.cs_circ_apply_T_direct(FAKE, 4096, 4, FAKE, NULL, NULL) == _lib.CS_EINVAL
+
+
+def test_workspace_bytes_layout():
+    """The block of one (n, d) plan: barrier area (counters and error flag),
+    scalars, six twiddle tables, the spectrum buffer and the c_hat and
+    y_hat tables, each part rounded up to 64 complex values."""
+    lib = cs.load()
+    up = lambda v: (v + 63) // 64 * 64
+    for n in (256, 4096, 1 << 17, 1 << 22):
+        N = n // 2
+        L = N.bit_length() - 1
+        N1 = 1 << ((L - 1) // 2) if L % 2 else 1 << (L // 2 - 1)
+        N2 = N // N1
+        lo = (L + 1) // 2
+        bar_words = 256 * 32 + 32
+        parts = [up(bar_words // 2), 64, up(N1), up(N2), up(1 << lo), up(N >> lo), up(N1), up(N2),
+                 up(N), up(N + 1), up(N + 1)]
+        for d in (2, 4, 8, 16):
+            for mode in (0, 1, 2):
+                assert lib.cs_workspace_bytes(n, d, mode) == 8 * sum(parts)
+    assert lib.cs_workspace_bytes(1 << 22, 4, 3) == 0
+    assert lib.cs_workspace_bytes(1000, 4, 1) == 0
+    assert lib.cs_workspace_bytes(4096, 3, 1) == 0
+    assert lib.cs_workspace_bytes(1 << 26, 4, 1) == 0
+
+
+def test_bad_workspace_rejected():
+    lib = cs.load()
+    # misaligned: rejected before any device query
+    assert lib.cs_set_workspace(ctypes.c_void_p(0x1000 + 8), 1 << 20) == _lib.CS_EINVAL
+    assert b"aligned" in lib.cs_last_error()
+    # smaller than the smallest plan
+    assert lib.cs_set_workspace(ctypes.c_void_p(0x1000), 1024) == _lib.CS_EINVAL
+    assert b"smallest" in lib.cs_last_error()

@@ -135,8 +135,7 @@ def test_shared_c_batch_shape_forward_and_aggregate_gradients():
     assert c.shape[0] == 1 << 16
     op = fftref.Operator(c.astype(np.float64), d)
     Y = np.stack([op.A(x.astype(np.float64)) for x in Xs]).astype(np.float32)
-    lam0 = 0.01 * np.mean([np.max(np.abs(op.AT(y.astype(np.float64)))) for y in Y])
-    lam = np.full(K, lam0, np.float32)
+    lam = np.full(K, unrolled_lam0(op, Y, 0.01), np.float32)
     tau = np.full(K, 1.0 / op.max_chat_sq(), np.float32)
     xK, ckpt = cs.unrolled_ista_fwd(g(c), d, g(Y), g(lam), g(tau), K, every)
     XK, _ = unrolled.forward(op, Y.astype(np.float64), lam.astype(np.float64), tau.astype(np.float64), K)
@@ -146,7 +145,7 @@ def test_shared_c_batch_shape_forward_and_aggregate_gradients():
     gl, gt, gy = cs.unrolled_ista_bwd(g(c), d, g(Y), g(lam), g(tau), K, every, ckpt, g(2.0 * (XK - Xs)))
     rl, rt, ry = unrolled.backward(op, Y.astype(np.float64), lam.astype(np.float64), tau.astype(np.float64), K, Xs)
     print("shared_c_batch-shaped: rel err lam %.2e tau %.2e y %.2e" % (rel(h(gl), rl), rel(h(gt), rt), rel(h(gy), ry)))
-    assert rel(h(gl), rl) <= 1e-3 and rel(h(gt), rt) <= 1e-3 and rel(h(gy), ry) <= 1e-3
+    assert rel(h(gl), rl) <= 1e-4 and rel(h(gt), rt) <= 1e-4 and rel(h(gy), ry) <= 1e-4
 
 
 def test_unrolled_bad_arguments():
@@ -161,35 +160,42 @@ def test_unrolled_bad_arguments():
         cs.unrolled_ista_fwd(c, 4, y, g(np.zeros(0)), g(np.zeros(0)), 0, 2)
 
 
-def test_shared_c_batch_full_size_sampled():
+def unrolled_lam0(op, Y, frac):
+    """lam_t initial value: frac * mean over the batch of ||A^T y_b||_inf."""
+    return frac * float(np.mean([np.max(np.abs(op.AT(y.astype(np.float64)))) for y in Y]))
+
+
+@pytest.mark.timeout(900)
+def test_shared_c_batch_full_size():
     """The timed configuration itself: all 64 signals (n = 2^16, d = 4,
-    K = 50, checkpoints every 10) in one forward and one backward call.
-    Sampled signals against the oracle (x_K and the y gradient of each are
-    that signal's own); the lam / tau gradients, sums over the batch, equal
-    the sums of the gradients of the two halves of the batch."""
+    K = 50, checkpoints every 10) in one forward and one backward call,
+    every signal against the FP64 oracle: x_K and dL/dy per signal, and the
+    batch's lam / tau gradients, at 1e-4.  Extra: the lam / tau gradients
+    equal the sums over the two halves of the batch."""
     prm = workloads.SHARED_C_PARAMS
     K, every, d = prm["K"], prm["every"], 4
     c, Xs = workloads.shared_c_batch()
     B = Xs.shape[0]
     op = fftref.Operator(c.astype(np.float64), d)
     Y = np.stack([op.A(x.astype(np.float64)) for x in Xs]).astype(np.float32)
-    lam0 = prm["lam_frac"] * max(float(np.max(np.abs(op.AT(y.astype(np.float64))))) for y in Y)
-    lam = np.full(K, lam0, np.float32)
+    lam = np.full(K, unrolled_lam0(op, Y, prm["lam_frac"]), np.float32)
     tau = np.full(K, 1.0 / op.max_chat_sq(), np.float32)
     xK, ckpt = cs.unrolled_ista_fwd(g(c), d, g(Y), g(lam), g(tau), K, every)
     xK = h(xK)
-    pick = [0, 21, 42, B - 1]
-    args = (lam.astype(np.float64), tau.astype(np.float64), K)
-    XKs, _ = unrolled.forward(op, Y[pick].astype(np.float64), *args)
-    for j, b in enumerate(pick):
-        assert rel(xK[b], XKs[j]) <= 1e-4, (b, rel(xK[b], XKs[j]))
-    # the sampled signals' loss gradient is the oracle's, the others' the GPU's
-    gx = 2.0 * (xK - Xs)
-    gx[pick] = 2.0 * (XKs - Xs[pick])
+    args = (op, Y.astype(np.float64), lam.astype(np.float64), tau.astype(np.float64), K)
+    XK, _ = unrolled.forward(*args)
+    ex = max(rel(xK[b], XK[b]) for b in range(B))
+    assert ex <= 1e-4, ex
+    # the loss gradient at x_K is the oracle's, so the backward passes differ
+    # only by their own arithmetic
+    gx = 2.0 * (XK - Xs)
     gl, gt, gy = (h(v) for v in cs.unrolled_ista_bwd(g(c), d, g(Y), g(lam), g(tau), K, every, ckpt, g(gx)))
-    _, _, ry = unrolled.backward(op, Y[pick].astype(np.float64), *args, Xs[pick])
-    for j, b in enumerate(pick):
-        assert rel(gy[b], ry[j]) <= 1e-3, (b, rel(gy[b], ry[j]))
+    rl, rt, ry = unrolled.backward(*args, Xs)
+    el, et = rel(gl, rl), rel(gt, rt)
+    ey = max(rel(gy[b], ry[b]) for b in range(B))
+    print("64 x 2^16 unrolled: worst x_K rel err %.2e; gradients rel err lam %.2e tau %.2e, worst dL/dy row %.2e"
+          % (ex, el, et, ey))
+    assert el <= 1e-4 and et <= 1e-4 and ey <= 1e-4
     halves = []
     for sl in (slice(0, B // 2), slice(B // 2, B)):
         xh, ch = cs.unrolled_ista_fwd(g(c), d, g(Y[sl]), g(lam), g(tau), K, every)
