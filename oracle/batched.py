@@ -1,9 +1,9 @@
-"""Batched ISTA in the FP64 oracle (test infrastructure).
+"""Batched ISTA and ADMM in the FP64 oracle (test infrastructure).
 
 Batching changes nothing about each signal's problem: the batched solve is
-the plain ISTA of Alg. 1 run independently on every signal (dense A for
-n <= 8192, the FFT reference above that), which the single-signal pins
-already fix.
+the plain ISTA of Alg. 1 (or ADMM of Alg. 2 with its own rho) run
+independently on every signal (dense A for n <= 8192, the FFT reference
+above that), which the single-signal pins already fix.
 """
 from __future__ import annotations
 
@@ -28,6 +28,19 @@ def ista_one(pr, iters):
 def ista_batched(problems, iters):
     """x(iters) of every signal, in order."""
     return [ista_one(pr, iters) for pr in problems]
+
+
+def admm_one(pr, rho, iters):
+    """(x, z, u) after `iters` ADMM steps from zero."""
+    y = pr.y.astype(np.float64)
+    if pr.n <= problem.DENSE_MAX:
+        return dense.admm(pr.A(), y, float(pr.lam), float(rho), iters)
+    return fftref.admm(pr.op(), y, float(pr.lam), float(rho), iters)
+
+
+def admm_batched(problems, rhos, iters):
+    """(x, z, u) of every signal, in order; rhos[i] is signal i's rho."""
+    return [admm_one(pr, r, iters) for pr, r in zip(problems, rhos)]
 
 
 def concat(problems):

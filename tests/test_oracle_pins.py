@@ -640,6 +640,32 @@ def test_batched_equals_one_by_one():
     check_batched_one_by_one(__import__("oracle.batched", fromlist=["ista_batched"]).ista_batched)
 
 
+def test_batched_admm_equals_one_by_one():
+    """Batched ADMM: signal i runs Alg. 2 with its own rho_i.  The reference
+    for the dense-size signals is the inverse of A^T A + rho_i I written out
+    here; the long signal's is the FFT reference's own ADMM."""
+    from oracle import batched
+    sigs = [workloads.signal(n, 4, max(1, n // 256), 70 + i) for i, n in enumerate((256, 1024, 16384))]
+    probs = batched.build_batch(sigs)
+    rhos = [0.5, 1.0, 2.0]
+    out = batched.admm_batched(probs, rhos, 25)
+    for pr, rho, (xb, zb, ub) in zip(probs, rhos, out):
+        y = pr.y.astype(np.float64)
+        lam = float(pr.lam)
+        if pr.n <= 1024:
+            A = dense.dense_A(pr.c.astype(np.float64), pr.d)
+            Minv = np.linalg.inv(A.T @ A + rho * np.eye(pr.n))
+            aty = A.T @ y
+            x = z = u = np.zeros(pr.n)
+            for _ in range(25):
+                x = Minv @ (aty + rho * (z - u))
+                z = dense.soft(x + u, lam / rho)
+                u = u + x - z
+        else:
+            x, z, u = fftref.admm(pr.op(), y, lam, rho, 25)
+        assert _rel(xb, x) < 1e-10 and _rel(zb, z) < 1e-10 and _rel(ub, u) < 1e-10
+
+
 def _mut_batched_shared_params(problems, iters):
     from oracle import batched
     p0 = problems[0]

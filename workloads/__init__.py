@@ -17,6 +17,8 @@ nonzeros at random positions, a Gaussian circulant generator) at these sizes:
                   k_i=n_i/256
   shared_c_batch  shared generator, n=2^16, d=4, batch 64 signals with k=256
   deblur_field    1024x1024 field vectorised, 10% lognormal pixels, d=2
+  random_rows_signal  1-D draw with a random row set Omega (|Omega| = m)
+                  for the circulant ADMM of Section 4.3
 
 Every draw is made in float64 and then rounded to float32 (the arrays handed to
 both sides are those float32 values).  The generator c has entries
@@ -177,3 +179,30 @@ def deblur_field(seed_offset: int = 0, side: int = 1024, frac: float = 0.1):
 
 
 DEBLUR1D_PARAMS = dict(L=5, admm_iters=300, rho=1.0, lam=1e-2)
+
+
+def random_rows_signal(n: int, m: int, k: int, seed: int):
+    """A 1-D draw for the random-row partial circulant of Section 4.3: c ~
+    N(0, 1/m) (length n), a support of k distinct positions with N(0,1)
+    values, then Omega, m distinct rows out of n (sorted).  Returns
+    (Signal1D with d = 0, omega)."""
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal(n) / np.sqrt(m)
+    supp = rng.choice(n, k, replace=False)
+    vals = rng.standard_normal(k)
+    omega = np.sort(rng.choice(n, m, replace=False)).astype(np.int64)
+    x = np.zeros(n)
+    x[supp] = vals
+    sig = Signal1D(n=n, d=0, k=k, c=_f32(c), x_true=_f32(x), support=np.sort(supp.astype(np.int64)))
+    return sig, omega
+
+
+def random_rows_large(seed_offset: int = 0):
+    """The random-row workload at the large single-signal size: n = 2^22,
+    m = n/2 rows drawn at random, k = n/10 nonzeros (the paper's Section 6
+    proportions m = n/2, k about n/10)."""
+    n = 1 << 22
+    return random_rows_signal(n, n // 2, n // 10, SEED_BASE + 7 + seed_offset)
+
+
+RANDOM_ROWS_PARAMS = dict(alpha_frac=0.01, rho=1.0, sigma=1.0, tau=1.0, iters=100)
