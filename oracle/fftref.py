@@ -100,7 +100,7 @@ def ista(op, y, lam, tau, iters, record=False, record_every=1, callback=None):
 
 
 def admm(op, y, lam, rho, iters, record=False, record_every=1,
-         x0=None, z0=None, u0=None):
+         x0=None, z0=None, u0=None, callback=None):
     """ADMM, Alg. 2, with B = (A^T A + rho I)^{-1} applied by Woodbury."""
     y = np.asarray(y, dtype=np.float64)
     n = op.n
@@ -115,4 +115,6 @@ def admm(op, y, lam, rho, iters, record=False, record_every=1,
         u = u + x - z
         if record and (t % record_every == 0):
             hist.append((t, x.copy(), z.copy(), u.copy()))
+        if callback is not None:
+            callback(t, x, z, u)
     return ((x, z, u), hist) if record else (x, z, u)

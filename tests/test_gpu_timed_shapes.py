@@ -13,6 +13,9 @@ oracle in FP64 (1/2 ||y - A x||^2 + lam ||x||_1).  Each test prints its worst
 error.  The oracle runs once per workload (module fixtures, about 1-2
 minutes each on one host core for the FFT references).
 """
+import sys
+import time
+
 import numpy as np
 import pytest
 
@@ -42,6 +45,17 @@ def h(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
+def progress(tag, every=25):
+    """Callback for the oracle loops: one line on stderr every `every`
+    iterations, so a long FP64 reference shows that it is moving."""
+    t0 = time.perf_counter()
+
+    def cb(t, *_):
+        if t % every == 0:
+            print("[oracle %s] t=%d (%.0fs)" % (tag, t, time.perf_counter() - t0), file=sys.stderr, flush=True)
+    return cb
+
+
 def rel(a, b):
     a, b = np.ravel(a), np.ravel(b)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
@@ -62,8 +76,13 @@ def large_ista_oracle(large):
     T = workloads.LARGE_PARAMS["ista_iters"]
     keep = set(T_CHECK) | {T}
     hist = {}
-    fftref.ista(op, pr.y.astype(np.float64), float(pr.lam), float(pr.tau), T,
-                callback=lambda t, x: hist.__setitem__(t, x.copy()) if t in keep else None)
+    tick = progress("n=2^22 ISTA")
+
+    def cb(t, x):
+        tick(t)
+        if t in keep:
+            hist[t] = x.copy()
+    fftref.ista(op, pr.y.astype(np.float64), float(pr.lam), float(pr.tau), T, callback=cb)
     return hist
 
 
@@ -71,10 +90,16 @@ def large_ista_oracle(large):
 def large_admm_oracle(large):
     pr, op = large
     T = workloads.LARGE_PARAMS["admm_iters"]
-    _, hist = fftref.admm(op, pr.y.astype(np.float64), float(pr.lam), workloads.LARGE_PARAMS["rho"], T,
-                          record=True)
     keep = set(T_CHECK) | {T}
-    return {t: (x, z) for (t, x, z, u) in hist if t in keep}
+    hist = {}
+    tick = progress("n=2^22 ADMM")
+
+    def cb(t, x, z, u):
+        tick(t)
+        if t in keep:
+            hist[t] = (x.copy(), z.copy())
+    fftref.admm(op, pr.y.astype(np.float64), float(pr.lam), workloads.LARGE_PARAMS["rho"], T, callback=cb)
+    return hist
 
 
 @pytest.mark.timeout(900)
@@ -132,7 +157,7 @@ def scene():
     op = pr.op()
     T = workloads.SCENE2D_PARAMS["admm_iters"]
     _, hist = twod.admm(op, pr.y.astype(np.float64).ravel(), float(pr.lam), workloads.SCENE2D_PARAMS["rho"], T,
-                        record=True, record_every=100)
+                        record=True, record_every=100, callback=progress("4096^2 ADMM"))
     return pr, op, {t: (x, z) for (t, x, z, u) in hist}
 
 
@@ -166,7 +191,8 @@ def test_deblur_1d_final_objective():
     c64 = sig.c.astype(np.float64)
     c_in = np.mean([np.roll(c64, -t) for t in range(prm["L"])], axis=0).astype(np.float32)
     lam, rho, T = prm["lam"], prm["rho"], prm["admm_iters"]
-    (xo, zo, uo), hist = fftref.admm(op, y.astype(np.float64), lam, rho, T, record=True, record_every=100)
+    (xo, zo, uo), hist = fftref.admm(op, y.astype(np.float64), lam, rho, T, record=True, record_every=100,
+                                     callback=progress("deblur 1-D ADMM", every=100))
     x, z, u = (h(v) for v in cs.admm_solve(g(c_in), sig.d, g(y), lam, rho, T))
     y64 = y.astype(np.float64)
     fg = fftref.objective(op, y64, lam, z)
