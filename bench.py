@@ -254,8 +254,11 @@ def main():
 
 def bench_batched(cs, torch, dev, steps, warmup):
     """512 signals, n_i = 2^12 .. 2^18 drawn uniformly in the exponent, d = 4,
-    k_i = n_i/256, per-signal lam and tau, ISTA 200 iterations, one launch.
-    Inputs (y, tau, lam) computed with the library's operators."""
+    k_i = n_i/256, per-signal lam and tau: ISTA 200 iterations, and ADMM
+    (rho = 1) 200 iterations on the same batch, each one persistent launch
+    replayed from a HIP graph.  Inputs (y, tau, lam) computed with the
+    library's operators.  The first call of each builds the plan and runs the
+    schedule tuner (warm-up, untimed)."""
     import numpy as np
     import workloads
     sigs = workloads.uneven_batch()
@@ -275,30 +278,45 @@ def bench_batched(cs, torch, dev, steps, warmup):
         cs.circ_apply(ci, d, x_true[off_n[i]:off_n[i] + n], yi)
         tau[i] = 1.0 / cs.circ_norm_bound(ci)[0]
         lam[i] = workloads.UNEVEN_PARAMS["lam_frac"] * cs.circ_apply_T(ci, d, yi).abs().max()
+    rho = torch.ones(len(sigs), device=dev)
     x_cat = torch.empty_like(c_cat)
-    run = lambda: cs.ista_solve_batched(ns, d, c_cat, y_cat, lam, tau, iters, x_cat)
-    for _ in range(max(1, warmup)):
-        run()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        run()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    cs.check_device()
+    z_cat, u_cat = torch.empty_like(c_cat), torch.empty_like(c_cat)
+
+    def timed(run):
+        for _ in range(max(1, warmup)):
+            run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        cs.check_device()
+        return e0.elapsed_time(e1) / steps
+
     sum_n = int(ns.sum())
-    # per signal and iteration: row pass 12n + 4m, column pass 16n (the
-    # iterate lives in the output slice)
+    # per signal and iteration: row pass Y read + write 8n, c_hat 4n, y_hat
+    # 4m; column pass Y read + write 8n and the iterate (ISTA x, ADMM u)
+    # read + write 8n
     bytes_it = int(sum(28 * int(n) + 4 * int(n) // d for n in ns))
-    return {"workload": "512 signals, n_i = 2^12..2^18 (uniform exponent), d=4, k_i=n_i/256, ISTA 200 it",
-            "signals": len(sigs), "sum_n": sum_n, "iters": iters, "ms_per_solve": ms,
-            "signals_per_s": len(sigs) / (ms / 1e3),
-            "signal_iterations_per_s": len(sigs) * iters / (ms / 1e3),
-            "model_GBs": bytes_it * iters / (ms / 1e3) / 1e9,
-            "compulsory_GBs": 13 * sum_n * iters / (ms / 1e3) / 1e9,
-            "equiv_n2e22_it_s": sum_n * iters / (1 << 22) / (ms / 1e3)}
+
+    def rates(ms, what):
+        return {"workload": "512 signals, n_i = 2^12..2^18 (uniform exponent), d=4, k_i=n_i/256, %s" % what,
+                "signals": len(sigs), "sum_n": sum_n, "iters": iters, "ms_per_solve": ms,
+                "signals_per_s": len(sigs) / (ms / 1e3),
+                "signal_iterations_per_s": len(sigs) * iters / (ms / 1e3),
+                "model_GBs": bytes_it * iters / (ms / 1e3) / 1e9,
+                "compulsory_GBs": 13 * sum_n * iters / (ms / 1e3) / 1e9,
+                "equiv_n2e22_it_s": sum_n * iters / (1 << 22) / (ms / 1e3)}
+
+    ms = timed(lambda: cs.ista_solve_batched(ns, d, c_cat, y_cat, lam, tau, iters, x_cat))
+    out = rates(ms, "ISTA %d it" % iters)
+    out["schedule"] = cs.batched_schedule()
+    ms_a = timed(lambda: cs.admm_solve_batched(ns, d, c_cat, y_cat, lam, rho, iters, x_cat, z_cat, u_cat))
+    out["admm"] = rates(ms_a, "ADMM rho=1, %d it" % iters)
+    out["admm"]["schedule"] = cs.batched_schedule()
+    return out
 
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X fp32 vector peak (counts packed FP32; these kernels are built without it)

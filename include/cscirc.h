@@ -113,27 +113,55 @@ cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, fl
                         float* obj, cs_stream stream);
 
 /* Batched ISTA (Alg. 1) over `count` independent signals of different
- * lengths, in one launch.  Signal i has length n_host[i] (a power of two in
- * [2^10, 2^18]), its own generator c_cat[off_n_host[i] .. + n), measurements
- * y_cat[off_m_host[i] .. + n/d), threshold parameters lambda_dev[i] and
- * tau_dev[i] (device arrays of `count` floats) and output / iterate
- * x_cat[off_n_host[i] .. + n); d (2, 4 or 8) is shared.  n_host and the
- * offsets are HOST arrays; off_n must be even.  Output slices must not
- * overlap.  Each signal is solved with the same arithmetic as cs_ista_solve,
- * from x(0) = 0, for `iters` iterations.  Signals with n < 2^14 are solved
- * in one launch whose workgroups take whole signals from a work queue,
- * longest first; longer signals are grouped by length, and each group runs
- * the row and column passes over all its signals at once (two launches per
- * iteration, plus a gather of the group's inputs and a scatter of its
- * outputs).  Per-device scratch (about 3n complex per short signal; for the
- * groups, copies and tables of at most 2 GiB at a time) is allocated on
- * first use and grown when a larger batch comes, and signal descriptors are
- * uploaded with a synchronous copy when they change; batched calls on one
- * device must be serialised.  */
-cs_status cs_ista_solve_batched(int32_t count, const int64_t* n_host, int32_t d, const int64_t* off_n_host,
-                                const int64_t* off_m_host, const float* c_cat, const float* y_cat,
-                                const float* lambda_dev, const float* tau_dev, int32_t iters, float* x_cat,
-                                cs_stream stream);
+ * lengths and decimations, in one persistent launch.
+ *
+ * Signal i has length n_host[i] (a power of two in [2^10, 2^18]) and
+ * decimation d_host[i] (2, 4 or 8; m_i = n_i / d_i); its generator is
+ * c_cat[off_n_host[i] .. + n_i), its measurements y_cat[off_m_host[i] .. +
+ * m_i), its parameters lambda_dev[i] and tau_dev[i] (device arrays of `count`
+ * floats, lambda >= 0, tau > 0) and its output x_cat[off_n_host[i] .. + n_i).
+ * n_host, d_host and the offsets are HOST arrays; off_n must be even and the
+ * n-length output slices must not overlap (CS_EINVAL otherwise).  Each signal
+ * is solved with the arithmetic of cs_ista_solve, from x(0) = 0, for `iters`
+ * iterations (iters == 0 writes x = 0).
+ *
+ * The whole batch is one cooperative launch: every workgroup owns row and
+ * column items of one size class (length and decimation) for the whole
+ * solve, and all signals advance together, one grid barrier after each pass.
+ * A plan per batch shape (device, lengths, decimations, offsets) holds the
+ * spectra and tables of every signal (about 12 n_i bytes each), allocated on
+ * the first call and kept (the four most recently used plans are kept).  On
+ * that first call a tuner times the candidate schedules (workgroups per CU;
+ * the cost model that shares workgroups among size classes) with a few
+ * iterations into a temporary block (the caller's outputs are not written),
+ * synchronising the stream; if the environment variable CSCIRC_TUNE_CACHE
+ * names a file, choices are read from and appended to it.  The launch is
+ * recorded in a HIP graph once per (plan, iters) and replayed.  A change of
+ * device pointers since the previous call uploads the signal descriptors
+ * with a synchronous copy.  Batched calls on one device must be serialised.
+ * A barrier wait that exceeds its bound is reported by cs_check_device.  */
+cs_status cs_ista_solve_batched(int32_t count, const int64_t* n_host, const int32_t* d_host,
+                                const int64_t* off_n_host, const int64_t* off_m_host, const float* c_cat,
+                                const float* y_cat, const float* lambda_dev, const float* tau_dev, int32_t iters,
+                                float* x_cat, cs_stream stream);
+
+/* Batched ADMM (Alg. 2, the x-update by Woodbury as in cs_admm_solve) over
+ * independent signals, in one persistent launch, with the same batch layout,
+ * plan, tuner and graph as cs_ista_solve_batched.  Per signal: lambda_dev[i]
+ * >= 0 and rho_dev[i] > 0 (device arrays); outputs x, z, u (n_i each) at
+ * off_n_host[i] of x_cat, z_cat, u_cat.  warm == 0 starts from x = z = u = 0
+ * (Alg. 2's initial guess); warm != 0 starts from the z and u passed in.
+ * iters == 0: cold writes x = z = u = 0, warm leaves them as passed.  */
+cs_status cs_admm_solve_batched(int32_t count, const int64_t* n_host, const int32_t* d_host,
+                                const int64_t* off_n_host, const int64_t* off_m_host, const float* c_cat,
+                                const float* y_cat, const float* lambda_dev, const float* rho_dev, int32_t iters,
+                                int32_t warm, float* x_cat, float* z_cat, float* u_cat, cs_stream stream);
+
+/* The schedule of the last batched call as a JSON object (grid, workgroups
+ * per CU, cost model, whether a graph was replayed, the shape key and the
+ * tuner's trials with their times), copied into buf (cap bytes, NUL
+ * included).  CS_EINVAL if buf is NULL or too small.  */
+cs_status cs_batched_schedule(char* buf, size_t cap);
 
 /* Differentiable unrolled ISTA (Alg. 1 with learnable per-iteration
  * parameters) over a batch of Bt signals that share one operator A = P C:

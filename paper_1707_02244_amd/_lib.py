@@ -17,7 +17,8 @@ CS_OK, CS_EINVAL, CS_ENOMEM, CS_EHIP, CS_ENOTSUP = 0, -1, -2, -3, -4
 _NAMES = {CS_EINVAL: "CS_EINVAL", CS_ENOMEM: "CS_ENOMEM", CS_EHIP: "CS_EHIP", CS_ENOTSUP: "CS_ENOTSUP"}
 
 EXPORTS = ["cs_circ_apply", "cs_circ_apply_T", "cs_circ_apply_direct", "cs_circ_apply_T_direct", "cs_circ_norm_bound", "cs_ista_solve",
-           "cs_admm_solve", "cs_ista_solve_batched", "cs_unrolled_ckpt_bytes", "cs_unrolled_ista_fwd",
+           "cs_admm_solve", "cs_ista_solve_batched", "cs_admm_solve_batched", "cs_batched_schedule",
+           "cs_unrolled_ckpt_bytes", "cs_unrolled_ista_fwd",
            "cs_unrolled_ista_bwd", "cs2_apply", "cs2_apply_T", "cs2_norm_bound", "cs2_ista_solve",
            "cs2_admm_solve", "cs_workspace_bytes", "cs_set_workspace", "cs_set_solver_path", "cs_check_device",
            "cs_timing_enable",
@@ -51,7 +52,9 @@ def load():
         "cs_circ_norm_bound": [P, I64, P, P],
         "cs_ista_solve": [P, I64, I32, P, F, F, I32, P, P, P],
         "cs_admm_solve": [P, I64, I32, P, F, F, I32, I32, P, P, P, P, P],
-        "cs_ista_solve_batched": [I32, P, I32, P, P, P, P, P, P, I32, P, P],
+        "cs_ista_solve_batched": [I32, P, P, P, P, P, P, P, P, I32, P, P],
+        "cs_admm_solve_batched": [I32, P, P, P, P, P, P, P, P, I32, I32, P, P, P, P],
+        "cs_batched_schedule": [ctypes.c_char_p, ctypes.c_size_t],
         "cs_unrolled_ckpt_bytes": [I64, I32, I32, I32, I32],
         "cs_unrolled_ista_fwd": [P, I64, I32, I32, P, P, P, I32, I32, P, P, P],
         "cs_unrolled_ista_bwd": [P, I64, I32, I32, P, P, P, I32, I32, P, P, P, P, P, P],
@@ -246,32 +249,69 @@ def admm_solve2(s, h, y, lam, rho, iters, x=None, z=None, u=None, warm=False, ob
     return x, z, u
 
 
-def batch_offsets(ns, d):
-    """Offsets of each signal in the concatenated n- and m-length arrays."""
+def _batch_dims(ns, d):
     import numpy as np
-    ns = np.asarray(ns, dtype=np.int64)
+    ns = np.ascontiguousarray(ns, dtype=np.int64)
+    ds = np.ascontiguousarray(np.broadcast_to(np.asarray(d, dtype=np.int32), ns.shape), dtype=np.int32)
+    return ns, ds
+
+
+def batch_offsets(ns, d):
+    """Offsets of each signal in the concatenated n- and m-length arrays
+    (d: one decimation for all signals, or one per signal)."""
+    import numpy as np
+    ns, ds = _batch_dims(ns, d)
     off_n = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)
-    off_m = np.concatenate([[0], np.cumsum(ns // d)[:-1]]).astype(np.int64)
+    off_m = np.concatenate([[0], np.cumsum(ns // ds)[:-1]]).astype(np.int64)
     return off_n, off_m
 
 
 def ista_solve_batched(ns, d, c_cat, y_cat, lam, tau, iters, x_cat=None):
-    """Batched ISTA over signals of lengths `ns` (concatenated inputs); lam and
-    tau are device arrays with one value per signal."""
-    import numpy as np
+    """Batched ISTA over signals of lengths `ns` and decimations `d` (one
+    value or one per signal), inputs concatenated in order; lam and tau are
+    device arrays with one value per signal."""
     import torch
-    ns = np.ascontiguousarray(ns, dtype=np.int64)
-    off_n, off_m = batch_offsets(ns, d)
-    total_n, total_m = int(ns.sum()), int((ns // d).sum())
+    ns, ds = _batch_dims(ns, d)
+    off_n, off_m = batch_offsets(ns, ds)
+    total_n, total_m = int(ns.sum()), int((ns // ds).sum())
     if x_cat is None:
         x_cat = torch.empty(total_n, device=c_cat.device, dtype=torch.float32)
     B = len(ns)
     P = ctypes.c_void_p
     _check(load().cs_ista_solve_batched(
-        B, P(ns.ctypes.data), d, P(off_n.ctypes.data), P(off_m.ctypes.data),
+        B, P(ns.ctypes.data), P(ds.ctypes.data), P(off_n.ctypes.data), P(off_m.ctypes.data),
         _ptr(c_cat, "c_cat", total_n), _ptr(y_cat, "y_cat", total_m), _ptr(lam, "lam", B), _ptr(tau, "tau", B),
         int(iters), _ptr(x_cat, "x_cat", total_n), _stream(c_cat)))
     return x_cat
+
+
+def admm_solve_batched(ns, d, c_cat, y_cat, lam, rho, iters, x_cat=None, z_cat=None, u_cat=None, warm=False):
+    """Batched ADMM (per-signal lam and rho, device arrays) over signals laid
+    out as for ista_solve_batched; returns (x, z, u) concatenated."""
+    import torch
+    ns, ds = _batch_dims(ns, d)
+    off_n, off_m = batch_offsets(ns, ds)
+    total_n, total_m = int(ns.sum()), int((ns // ds).sum())
+    dev = c_cat.device
+    x_cat = torch.empty(total_n, device=dev, dtype=torch.float32) if x_cat is None else x_cat
+    z_cat = torch.zeros(total_n, device=dev, dtype=torch.float32) if z_cat is None else z_cat
+    u_cat = torch.zeros(total_n, device=dev, dtype=torch.float32) if u_cat is None else u_cat
+    B = len(ns)
+    P = ctypes.c_void_p
+    _check(load().cs_admm_solve_batched(
+        B, P(ns.ctypes.data), P(ds.ctypes.data), P(off_n.ctypes.data), P(off_m.ctypes.data),
+        _ptr(c_cat, "c_cat", total_n), _ptr(y_cat, "y_cat", total_m), _ptr(lam, "lam", B), _ptr(rho, "rho", B),
+        int(iters), 1 if warm else 0, _ptr(x_cat, "x_cat", total_n), _ptr(z_cat, "z_cat", total_n),
+        _ptr(u_cat, "u_cat", total_n), _stream(c_cat)))
+    return x_cat, z_cat, u_cat
+
+
+def batched_schedule():
+    """The last batched call's schedule and tuner trials (a dict)."""
+    import json
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(load().cs_batched_schedule(buf, len(buf)))
+    return json.loads(buf.value.decode())
 
 
 def unrolled_ckpt_bytes(n, d, batch, K, every):

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libcscirc.so")
 ROW_LENGTHS = [16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192]   # pass A (N2)
 COL_LENGTHS = [8, 16, 32, 64, 128, 256, 512, 1024, 2048]            # pass B (N1)
 SOLVE_LOGN = list(range(7, 22))                                     # persistent solver, N = 2^L
-BATCH_D2 = [1, 2, 4]                                                # batched ISTA, d = 2 * D2
+BATCH_ALG = [0, 1]                                                  # persistent batched solver: ISTA, ADMM
 COL2_LENGTHS = [16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192]  # 2-D column pass (rows R)
 ROW2_LENGTHS = [8, 16, 32, 64, 128, 256, 512, 1024, 2048]           # 2-D row pass (H = columns / 2)
 
@@ -59,8 +59,8 @@ def build(jobs: int | None = None, verbose: bool = False, incremental: bool = Fa
         units.append((os.path.join(CSRC, "inst_passB.hip"), os.path.join(BUILD, "passB_%d.o" % L), ["-DCS_LEN=%d" % L]))
     for L in SOLVE_LOGN:
         units.append((os.path.join(CSRC, "inst_solve.hip"), os.path.join(BUILD, "solve_%d.o" % L), ["-DCS_LOGN=%d" % L]))
-    for D2 in BATCH_D2:
-        units.append((os.path.join(CSRC, "inst_batch.hip"), os.path.join(BUILD, "batch_%d.o" % D2), ["-DCS_D2=%d" % D2]))
+    for A in BATCH_ALG:
+        units.append((os.path.join(CSRC, "inst_bpersist.hip"), os.path.join(BUILD, "bpersist_%d.o" % A), ["-DCS_ALG=%d" % A]))
     for L in COL2_LENGTHS:
         units.append((os.path.join(CSRC, "inst2d_col.hip"), os.path.join(BUILD, "col2_%d.o" % L), ["-DCS_LEN=%d" % L]))
     for L in ROW2_LENGTHS:
@@ -68,6 +68,7 @@ def build(jobs: int | None = None, verbose: bool = False, incremental: bool = Fa
     units.append((os.path.join(CSRC, "inst_direct.hip"), os.path.join(BUILD, "direct.o"), []))
     units.append((os.path.join(CSRC, "runtime.hip"), os.path.join(BUILD, "runtime.o"), []))
     units.append((os.path.join(CSRC, "runtime2d.hip"), os.path.join(BUILD, "runtime2d.o"), []))
+    units.append((os.path.join(CSRC, "runtime_batch.hip"), os.path.join(BUILD, "runtime_batch.o"), []))
     units.sort(key=lambda u: ("solve" not in u[1] and "batch" not in u[1], -len(u[1])))
     jobs = jobs or min(16, os.cpu_count() or 4)
     todo = [u for u in units if not incremental or _stale(u[0], u[1])]

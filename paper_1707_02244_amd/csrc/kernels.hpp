@@ -134,6 +134,59 @@ struct PassBArgs {
                            //   l1[b] = sum of |x| over workgroup b's samples
 };
 
+// Data that workgroups of one persistent launch exchange (the spectrum
+// buffer, and state a workgroup reads back in later iterations) is read and
+// written with relaxed agent-scope atomic accesses: on gfx950 these are
+// plain vector loads/stores carrying the device-coherence bit, so a value
+// stored by one XCD is what another XCD's load returns, without writing back
+// or invalidating any L2 (the read-only c_hat / y_hat tables keep their L2
+// residency across iterations).
+__device__ __forceinline__ float2 ld_coh(const float2* p) {
+  const uint64_t v = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return __builtin_bit_cast(float2, v);
+}
+__device__ __forceinline__ void st_coh(float2* p, float2 v) {
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), __builtin_bit_cast(uint64_t, v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Buffer accesses with the device-coherence cache bit (sc1): the same
+// coherence as the relaxed agent-scope atomics above, but as ordinary vector
+// memory instructions that the compiler issues back to back (the atomic forms
+// are kept in program order, one round trip each).  The resource covers the
+// array exactly, so an offset outside it reads zeros and drops the store.
+typedef unsigned cs_u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned cs_u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kCohAux = 16;                  // cache policy: sc1
+constexpr int kBufWord3 = 0x00020000;        // raw 32-bit buffer (gfx9 family)
+
+// Global float2 array access of the pass bodies: plain (COH = false, the
+// launch-per-pass kernels, where kernel boundaries order everything) or
+// device-coherent (persistent launches, whose workgroups exchange data
+// within one launch).  `count` is the array's length in float2.
+template <bool COH>
+struct Gf2 {
+  float2* p;
+  __device__ __forceinline__ Gf2(float2* base, unsigned) : p(base) {}
+  __device__ __forceinline__ float2 ld(size_t i) const { return p[i]; }
+  __device__ __forceinline__ void st(size_t i, float2 v) const { p[i] = v; }
+};
+template <>
+struct Gf2<true> {
+  __amdgpu_buffer_rsrc_t rs;
+  __device__ __forceinline__ Gf2(float2* base, unsigned count)
+      : rs(__builtin_amdgcn_make_buffer_rsrc(base, 0, (int)(count * 8u), kBufWord3)) {}
+  __device__ __forceinline__ float2 ld(size_t i) const {
+    const cs_u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, (unsigned)i * 8u, 0, kCohAux);
+    return c2(__uint_as_float(v.x), __uint_as_float(v.y));
+  }
+  __device__ __forceinline__ void st(size_t i, float2 v) const {
+    const cs_u32x2 w = {__float_as_uint(v.x), __float_as_uint(v.y)};
+    __builtin_amdgcn_raw_buffer_store_b64(w, rs, (unsigned)i * 8u, 0, kCohAux);
+  }
+};
+
 // Sum of v over the workgroup, returned to thread 0 (all threads call it).
 template <int T>
 __device__ __forceinline__ double block_sum(double v, unsigned tid) {
@@ -159,20 +212,33 @@ __device__ __forceinline__ float2 tw_N(const PassBArgs& a, int e) {
 // Pass A.  Workgroup w owns rows {w, N1 - w}; workgroup 0 owns the two rows
 // that are their own mirror images, {0, N1/2}.  Rows are held in LDS slots 0
 // and 1.
-template <int N2, int OP, int D2, int T>
-__device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __restrict__ lds,
+template <int N2, int OP, int D2, int T, bool COH = false, int AI = 1>
+__device__ __forceinline__ void rowpass(const PassAArgs& a, int w0, float2* __restrict__ lds,
                                         const float2* __restrict__ tws, unsigned tid) {
   constexpr int LD = N2 + kPadA;
-  constexpr int EPT = (2 * N2 + T - 1) / T;           // row elements per thread
+  constexpr int NR = 2 * AI * N2;                     // elements of the held rows
+  constexpr int EPT = (NR + T - 1) / T;               // row elements per thread
   constexpr bool GROUP = (OP == A_ISTA || OP == A_ADMM || OP == A_ADJ || OP == A_TILE || OP == A_RES);
   constexpr bool NEED_C = (OP == A_ISTA || OP == A_ADMM || OP == A_ADJ || OP == A_RES);
   constexpr bool HAS_RES = (OP == A_ISTA || OP == A_ADMM || OP == A_RES);
   constexpr int MC = N2 / D2;                         // alias classes per row (= m / N1)
-  constexpr int GPT = GROUP ? (MC + 1 + T - 1) / T : 1;
+  constexpr int GPT = GROUP ? (AI * MC + 1 + T - 1) / T : 1;
   const int N1 = a.N1;
   const float tau = a.tau_dev ? a.tau_dev[a.t] : a.tau;
-  const int ra = w;                          // row in slot 0
-  const int rb = w ? (N1 - w) : (N1 >> 1);   // row in slot 1
+  // AI consecutive row pairs from w0: LDS slot 2i holds row w = w0 + i, slot
+  // 2i + 1 its mirror N1 - w (N1/2 for w = 0)
+  auto row_of = [&](int slot) {
+    const int w = w0 + (slot >> 1);
+    return (slot & 1) ? (w ? N1 - w : (N1 >> 1)) : w;
+  };
+  // item g of a per-pair range of `span` entries (span + 1 for pair 0):
+  // its pair index pi and its index lc within the pair
+  auto split_item = [&](int g, int span, int& pi, int& lc) {
+    if (w0 == 0 && g <= span) { pi = 0; lc = g; }
+    else if (w0 == 0) { pi = 1 + (g - span - 1) / span; lc = (g - span - 1) % span; }
+    else { pi = g / span; lc = g % span; }
+  };
+  const Gf2<COH> Yg(a.Y, (unsigned)a.N);
 
   // Issue every global load before the first wait: the two rows and (update
   // modes) each class's c_hat, y_hat and split twiddles.
@@ -180,20 +246,23 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const int i = tid + k * T;
-    if ((2 * N2) % T == 0 || i < 2 * N2) {
+    if (NR % T == 0 || i < NR) {
       const int s = i / N2, p = i % N2;
-      rv[k] = a.Y[(size_t)(s ? rb : ra) * N2 + p];
+      rv[k] = Yg.ld((size_t)row_of(s) * N2 + p);
     }
   }
   // class decode: mode 0 = row pair (w > 0); 1 = row 0; 2 = row N1/2 (w = 0)
   float2 gca[GPT][D2], gcb[GPT][D2], gw[GPT][D2], gy[GPT];
   const int M = MC;
-  const int ng = w ? M : (M + 1);
+  const int ng = (w0 ? M : (M + 1)) + (AI - 1) * M;   // classes of the held pairs
   if constexpr (GROUP) {
 #pragma unroll
     for (int k = 0; k < GPT; ++k) {
-      const int g = tid + k * T;
-      if (g < ng) {
+      const int gi = tid + k * T;
+      if (gi < ng) {
+        int pi, g;
+        split_item(gi, M, pi, g);
+        const int w = w0 + pi;
         int rowa, k2, mode;
         if (w) { rowa = w; k2 = g; mode = 0; }
         else if (g <= (M >> 1)) { rowa = 0; k2 = g; mode = 1; }
@@ -218,10 +287,10 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const int i = tid + k * T;
-    if ((2 * N2) % T == 0 || i < 2 * N2) lds[lpr((i / N2) * LD + (i % N2))] = rv[k];
+    if (NR % T == 0 || i < NR) lds[lpr((i / N2) * LD + (i % N2))] = rv[k];
   }
   __syncthreads();
-  lds_fft<N2, 2, T, false, false, LD>(lds, tws, tid);
+  lds_fft<N2, 2 * AI, T, false, false, LD>(lds, tws, tid);
 
   // objective trace: this thread's sum of weight * |Y_hat - S|^2; a class
   // stands for m-point bins k' and m - k' (weight 2) unless k' is 0 or m/2
@@ -234,12 +303,15 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
     // N1/2 classes k2 in [0, M/2) (b positions N2-1-p in the same row).
 #pragma unroll
     for (int k = 0; k < GPT; ++k) {
-      const int g = tid + k * T;
-      if (g >= ng) continue;
+      const int gi = tid + k * T;
+      if (gi >= ng) continue;
+      int pi, g;
+      split_item(gi, M, pi, g);
+      const int w = w0 + pi;
       int sa, sb, k2, mode;
-      if (w) { sa = 0; sb = 1; k2 = g; mode = 0; }
-      else if (g <= (M >> 1)) { sa = 0; sb = 0; k2 = g; mode = 1; }
-      else { sa = 1; sb = 1; k2 = g - (M >> 1) - 1; mode = 2; }
+      if (w) { sa = 2 * pi; sb = 2 * pi + 1; k2 = g; mode = 0; }
+      else if (g <= (M >> 1)) { sa = 2 * pi; sb = 2 * pi; k2 = g; mode = 1; }
+      else { sa = 2 * pi + 1; sb = 2 * pi + 1; k2 = g - (M >> 1) - 1; mode = 2; }
       const bool write_b = !(mode == 1 && (k2 == 0 || k2 == (M >> 1)));
       const float res_w = write_b ? 2.0f : 1.0f;
       float2 Xa[D2], Xb[D2];
@@ -338,12 +410,15 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
     // pairs with slot 1 position N2-1-p.  w = 0: row 0 positions p in
     // [0, N2/2] pair with (N2 - p) mod N2 (p = 0 and N2/2 pair with
     // themselves), row N1/2 positions p < N2/2 pair with N2-1-p.
-    const int np = w ? N2 : (N2 + 1);
-    for (int g = tid; g < np; g += T) {
+    const int np = (w0 ? N2 : (N2 + 1)) + (AI - 1) * N2;
+    for (int gi = tid; gi < np; gi += T) {
+      int pi, g;
+      split_item(gi, N2, pi, g);
+      const int w = w0 + pi;
       int sa, sb, rowa, p, mode;
-      if (w) { sa = 0; sb = 1; rowa = w; p = g; mode = 0; }
-      else if (g <= (N2 >> 1)) { sa = 0; sb = 0; rowa = 0; p = g; mode = 1; }
-      else { sa = 1; sb = 1; rowa = N1 >> 1; p = g - (N2 >> 1) - 1; mode = 2; }
+      if (w) { sa = 2 * pi; sb = 2 * pi + 1; rowa = w; p = g; mode = 0; }
+      else if (g <= (N2 >> 1)) { sa = 2 * pi; sb = 2 * pi; rowa = 0; p = g; mode = 1; }
+      else { sa = 2 * pi + 1; sb = 2 * pi + 1; rowa = N1 >> 1; p = g - (N2 >> 1) - 1; mode = 2; }
       const int rowb = (mode == 0) ? (N1 - w) : rowa;
       const int q = (mode == 1) ? ((N2 - p) & (N2 - 1)) : (N2 - 1 - p);
       const bool write_b = !(mode == 1 && (p == 0 || p == (N2 >> 1)));
@@ -377,18 +452,18 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w, float2* __res
   if constexpr (HAS_RES) {
     if (a.res) {
       const double r = block_sum<T>(double(res_acc), tid);
-      if (tid == 0) a.res[w] = r;
+      if (tid == 0) a.res[w0] = r;   // (traces run with AI = 1)
     }
   }
   if constexpr (OP != A_SPEC && OP != A_RES) {
     __syncthreads();
-    lds_fft<N2, 2, T, true, false, LD>(lds, tws, tid);
+    lds_fft<N2, 2 * AI, T, true, false, LD>(lds, tws, tid);
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       const int i = tid + k * T;
-      if ((2 * N2) % T == 0 || i < 2 * N2) {
+      if (NR % T == 0 || i < NR) {
         const int s = i / N2, p = i % N2;
-        a.Y[(size_t)(s ? rb : ra) * N2 + p] = lds[lpr(s * LD + p)];
+        Yg.st((size_t)row_of(s) * N2 + p, lds[lpr(s * LD + p)]);
       }
     }
   }
@@ -446,37 +521,60 @@ __device__ __forceinline__ void adj_partials(const PassBArgs& a, double s_th, do
   __syncthreads();
 }
 
-template <int N1, int MODE, int T>
+// COH (persistent launches): device-coherent spectrum and state accesses, the
+// whole column block loaded at once, and the state (B_ISTA / B_ADMM) loaded
+// together with the spectrum instead of after the inverse transform.  TWL:
+// the four-step twiddles come from an LDS copy twn = [W_N^e, e < 2^lo_bits |
+// W_N^(e 2^lo_bits), e < N >> lo_bits] instead of the global tables.
+template <int N1, int MODE, int T, bool COH = false, int CBW = kColsPerBlock, bool TWL = false>
 __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __restrict__ lds,
-                                        const float2* __restrict__ tws, unsigned tid) {
-  constexpr int CB = kColsPerBlock;
+                                        const float2* __restrict__ tws, unsigned tid,
+                                        const float2* __restrict__ twn = nullptr) {
+  constexpr int CB = CBW;   // adjacent columns held, interleaved
   constexpr int NE = N1 * CB;
   constexpr int EPT = (NE + T - 1) / T;
-  constexpr int CH = EPT < 8 ? EPT : 8;
+  constexpr int CH = COH ? EPT : (EPT < 8 ? EPT : 8);
   constexpr bool FULL = (NE % T) == 0;
   const int j2_0 = blk * CB;
   const int N2 = a.N2;
+  const Gf2<COH> Yg(a.Y, (unsigned)a.N);
   constexpr bool HAS_INV = (MODE == B_ISTA || MODE == B_ADMM || MODE == B_OUT_ALL || MODE == B_OUT_DEC ||
                             MODE == B_ISTA_REC || MODE == B_ADJ_X || MODE == B_ADJ_XV);
+  constexpr bool STATE = (MODE == B_ISTA || MODE == B_ADMM || MODE == B_ISTA_REC);
+  constexpr bool PRE = COH && STATE;   // state loaded with the spectrum
+  auto twN = [&](int e) -> float2 {
+    if constexpr (TWL) {
+      e &= (a.N - 1);
+      return cmul(twn[e & ((1 << a.lo_bits) - 1)], twn[(1 << a.lo_bits) + (e >> a.lo_bits)]);
+    } else {
+      return tw_N(a, e);
+    }
+  };
+  const Gf2<COH> Sg(reinterpret_cast<float2*>(a.u), (unsigned)a.N);
+  float2 svp[PRE ? EPT : 1];
 
   if constexpr (HAS_INV) {
 #pragma unroll
     for (int k0 = 0; k0 < EPT; k0 += CH) {
-      float2 v[CH], t[CH];
+      float2 v[CH], t[TWL ? 1 : CH];
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const int i = tid + (k0 + k) * T;
         if (FULL || i < NE) {
           const int k1 = i / CB, c = i % CB;
           const int j2 = j2_0 + c;
-          v[k] = a.Y[(size_t)k1 * N2 + j2];
-          t[k] = tw_N(a, j2 * k1);
+          v[k] = Yg.ld((size_t)k1 * N2 + j2);
+          if constexpr (PRE) svp[k0 + k] = Sg.ld((size_t)k1 * N2 + j2);
+          if constexpr (!TWL) t[k] = twN(j2 * k1);
         }
       }
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const int i = tid + (k0 + k) * T;
-        if (FULL || i < NE) lds[lp(i)] = cmulc(v[k], t[k]);
+        if (FULL || i < NE) {
+          if constexpr (TWL) lds[lp(i)] = cmulc(v[k], twN((j2_0 + (i % CB)) * (i / CB)));
+          else lds[lp(i)] = cmulc(v[k], t[k]);
+        }
       }
     }
     __syncthreads();
@@ -487,7 +585,6 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
       // ISTA: lds holds tau A^T r and a.u is the iterate x.
       // ADMM: lds holds x(t) and a.u is the scaled dual u.
       const float thr = a.tau_dev ? a.tau_dev[a.t] * a.lam_dev[a.t] : a.thr;
-      float2* st = reinterpret_cast<float2*>(a.u);
       float l1_acc = 0.0f;   // objective trace: sum |x| of this thread's samples
 #pragma unroll
       for (int k0 = 0; k0 < EPT; k0 += CH) {
@@ -495,7 +592,8 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
           const int i = tid + (k0 + k) * T;
-          if (FULL || i < NE) sv[k] = st[(size_t)(i / CB) * N2 + j2_0 + (i % CB)];
+          if constexpr (PRE) sv[k] = svp[k0 + k];
+          else if (FULL || i < NE) sv[k] = Sg.ld((size_t)(i / CB) * N2 + j2_0 + (i % CB));
         }
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
@@ -507,7 +605,7 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
               const float2 v = cadd(sv[k], step);
               const float2 x = c2(soft(v.x, thr), soft(v.y, thr));
               l1_acc += fabsf(x.x) + fabsf(x.y);
-              st[j] = x;
+              Sg.st(j, x);
               lds[lp(i)] = x;
               if constexpr (MODE == B_ISTA_REC) {
                 reinterpret_cast<float2*>(a.rv)[j] = v;
@@ -519,7 +617,7 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
               const float2 xu = cadd(x, sv[k]);
               const float2 z = c2(soft(xu.x, thr), soft(xu.y, thr));
               const float2 u1 = csub(xu, z);
-              st[j] = u1;
+              Sg.st(j, u1);
               if (a.last) {
                 reinterpret_cast<float2*>(a.out0)[j] = x;
                 reinterpret_cast<float2*>(a.out1)[j] = z;
@@ -621,14 +719,14 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
       const int i = tid + (k0 + k) * T;
-      if (FULL || i < NE) t[k] = tw_N(a, (j2_0 + (i % CB)) * (i / CB));
+      if (FULL || i < NE) t[k] = twN((j2_0 + (i % CB)) * (i / CB));
     }
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
       const int i = tid + (k0 + k) * T;
       if (FULL || i < NE) {
         const int k1 = i / CB, c = i % CB;
-        a.Y[(size_t)k1 * N2 + j2_0 + c] = cmul(lds[lp(i)], t[k]);
+        Yg.st((size_t)k1 * N2 + j2_0 + c, cmul(lds[lp(i)], t[k]));
       }
     }
   }

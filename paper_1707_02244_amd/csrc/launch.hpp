@@ -28,13 +28,13 @@ hipError_t launch_solve(int alg, int d2, const SolveArgs& a, hipStream_t s);
 template <int LOGN>
 int solve_blocks_per_cu(int alg, int d2);
 
-struct BatchSig;
-// batched ISTA for decimation d = 2 * D2 (inst_batch.hip)
-template <int D2>
-hipError_t launch_batch_ista(const BatchSig* sigs, int count, unsigned* queue, int iters, int grid,
-                             hipStream_t s);
-template <int D2>
-int batch_blocks_per_cu();
+// persistent batched solver, ALG 0: ISTA, 1: ADMM (inst_bpersist.hip): the
+// kernel (launched cooperatively with one PBatchArgs argument) and how many
+// of its workgroups fit on one CU
+template <int ALG>
+const void* batch_persist_kernel();
+template <int ALG>
+int batch_persist_blocks_per_cu();
 
 struct Col2Args;
 struct Row2Args;

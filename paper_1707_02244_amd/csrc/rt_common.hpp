@@ -54,6 +54,10 @@ cs_status objective_reduce(const double* res, int nres, const double* l1, int nl
 // out[0] = max(out[0], max_i |t[i]|^2); out[0] must start >= 0.
 cs_status max_abs2(const float2* t, int count, float* out, hipStream_t s);
 
+// Error flags of the batched solves' plans on device `dev`: read, cleared,
+// reported as CS_EHIP if one was set (runtime_batch.hip).
+cs_status batch_check_flags(int dev);
+
 // Timed launch kinds (names as reported by cs_timing_read).
 enum TimedKind {
   T_A_ISTA = 0, T_B_ISTA, T_A_ADMM, T_B_ADMM, T_S_ISTA, T_S_ADMM, T_BATCH,

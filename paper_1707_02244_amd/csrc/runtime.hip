@@ -23,7 +23,6 @@
 #include "rt_common.hpp"
 #include "launch.hpp"
 #include "solve_persistent.hpp"
-#include "batch.hpp"
 #include "unrolled.hpp"
 
 #include <algorithm>
@@ -597,85 +596,6 @@ SolveArgs solve_args(const Plan& P) {
   return a;
 }
 
-// Batched solves: per device, a grow-only scratch buffer (spectrum and
-// tables of every signal), the descriptor array of the last batch and the
-// work-queue counter.
-// Where one long signal of a length group sits in the caller's arrays.
-struct GItem {
-  int64_t off_n, off_m;   // offsets in c / x and in y
-  int32_t idx;            // index into lambda / tau
-  int32_t pad;
-};
-
-struct BatchState {
-  void* scratch = nullptr;
-  size_t scratch_bytes = 0;
-  BatchSig* sigs = nullptr;
-  size_t sigs_cap = 0;
-  std::vector<BatchSig> last;   // descriptors currently on the device
-  unsigned* queue = nullptr;
-  void* gscratch = nullptr;     // grouped long signals: copies, spectra, tables
-  size_t gscratch_bytes = 0;
-  GItem* gitems = nullptr;
-  size_t gitems_cap = 0;
-  std::vector<GItem> glast;
-};
-
-// Signals from this length on are solved per length group (see
-// cs_ista_solve_batched).
-#ifndef CS_GROUP_MIN_LOGN
-#define CS_GROUP_MIN_LOGN 14
-#endif
-constexpr int64_t kGroupMinN = int64_t(1) << CS_GROUP_MIN_LOGN;
-constexpr size_t kGroupChunkBytes = size_t(1) << 31;
-
-// Copy a length group's inputs into contiguous per-group arrays (grid y =
-// signal of the group).
-__global__ void k_group_gather(const GItem* __restrict__ items, int64_t n, int64_t m, const float* __restrict__ c,
-                               const float* __restrict__ y, const float* __restrict__ lam,
-                               const float* __restrict__ tau, float* __restrict__ cg, float* __restrict__ yg,
-                               float* __restrict__ lamg, float* __restrict__ taug) {
-  const int64_t s = blockIdx.y;
-  const GItem it = items[s];
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-    cg[s * n + i] = c[it.off_n + i];
-    if (i < m) yg[s * m + i] = y[it.off_m + i];
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    lamg[s] = lam[it.idx];
-    taug[s] = tau[it.idx];
-  }
-}
-
-// Copy a length group's iterates back to the caller's x.
-__global__ void k_group_scatter(const GItem* __restrict__ items, int64_t n, const float* __restrict__ xg,
-                                float* __restrict__ x) {
-  const int64_t s = blockIdx.y;
-  const int64_t o = items[s].off_n;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    x[o + i] = xg[s * n + i];
-}
-auto& g_batch = *new std::map<int, BatchState>();
-
-hipError_t launch_batch_dispatch(int d2, const BatchSig* sigs, int count, unsigned* queue, int iters,
-                                 int grid, hipStream_t s) {
-  switch (d2) {
-    case 1: return launch_batch_ista<1>(sigs, count, queue, iters, grid, s);
-    case 2: return launch_batch_ista<2>(sigs, count, queue, iters, grid, s);
-    case 4: return launch_batch_ista<4>(sigs, count, queue, iters, grid, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-int batch_blocks_dispatch(int d2) {
-  switch (d2) {
-    case 1: return batch_blocks_per_cu<1>();
-    case 2: return batch_blocks_per_cu<2>();
-    case 4: return batch_blocks_per_cu<4>();
-    default: return 0;
-  }
-}
-
 cs_status check_common(const void* c, int64_t n, int d) {
   if (!c) return fail(CS_EINVAL, "c is NULL");
   if (!is_pow2(n) || n < kMinN || n > kMaxN)
@@ -886,237 +806,6 @@ extern "C" {
 const char* cs_last_error(void) { return g_err.c_str(); }
 
 int32_t cs_version(void) { return 100; }
-
-cs_status cs_ista_solve_batched(int32_t count, const int64_t* n_host, int32_t d, const int64_t* off_n_host,
-                                const int64_t* off_m_host, const float* c_cat, const float* y_cat,
-                                const float* lambda_dev, const float* tau_dev, int32_t iters, float* x_cat,
-                                cs_stream stream) {
-  if (count < 0) return fail(CS_EINVAL, "count=%d must be >= 0", count);
-  if (count == 0) { g_err.clear(); return CS_OK; }
-  if (!n_host || !off_n_host || !off_m_host) return fail(CS_EINVAL, "size or offset array is NULL");
-  if (!c_cat || !y_cat || !lambda_dev || !tau_dev || !x_cat) return fail(CS_EINVAL, "a device array is NULL");
-  if (d != 2 && d != 4 && d != 8) return fail(CS_EINVAL, "d=%d must be 2, 4 or 8 for batched solves", d);
-  if (iters < 0) return fail(CS_EINVAL, "iters=%d must be >= 0", iters);
-  for (int i = 0; i < count; ++i) {
-    const int64_t n = n_host[i];
-    if (!is_pow2(n) || n < (int64_t(1) << (kBMinLogN + 1)) || n > (int64_t(1) << (kBMaxLogN + 1)))
-      return fail(CS_EINVAL, "n[%d]=%lld must be a power of two in [2^%d, 2^%d]", i, (long long)n,
-                  kBMinLogN + 1, kBMaxLogN + 1);
-    if (off_n_host[i] < 0 || (off_n_host[i] & 1) || off_m_host[i] < 0)
-      return fail(CS_EINVAL, "offsets of signal %d must be >= 0 (off_n even)", i);
-  }
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  int dev = 0;
-  CS_HIP(hipGetDevice(&dev));
-  // tables per distinct length (the per-(n, d) plans)
-  std::map<int64_t, Plan*> plans;
-  for (int i = 0; i < count; ++i) {
-    if (plans.count(n_host[i])) continue;
-    Plan* P = nullptr;
-    cs_status st = get_plan(n_host[i], d, &P);
-    if (st != CS_OK) return st;
-    plans[n_host[i]] = P;
-  }
-  // Signals shorter than kGroupMinN go to the single-launch work-queue
-  // kernel (one workgroup per signal); longer ones are solved per length
-  // group with the row / column passes over the whole group (grid y =
-  // signal), so a group of long signals uses the whole GPU instead of one
-  // workgroup each.
-  std::vector<int> small;
-  std::map<int64_t, std::vector<int>> groups;
-  for (int i = 0; i < count; ++i) {
-    if (n_host[i] < kGroupMinN) small.push_back(i);
-    else groups[n_host[i]].push_back(i);
-  }
-  std::lock_guard<std::mutex> lk(g_mu);
-  BatchState& B = g_batch[dev];
-  cs_status st = CS_OK;
-  if (!small.empty()) {
-    // longest signals first: the queue hands them out first and the
-    // launch's tail is made of short signals
-    std::vector<int> order = small;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n_host[a] > n_host[b]; });
-    const int cs_ = int(order.size());
-    size_t need = 0;
-    std::vector<size_t> off(cs_);
-    for (int k = 0; k < cs_; ++k) {
-      const int64_t N = n_host[order[k]] / 2;
-      off[k] = need;
-      need += size_t((3 * N + 2 + 63) & ~int64_t(63)) * sizeof(float2);
-    }
-    if (B.scratch_bytes < need) {
-      CS_HIP(hipStreamSynchronize(s));
-      if (B.scratch) CS_HIP(hipFree(B.scratch));
-      B.scratch = nullptr;
-      B.scratch_bytes = 0;
-      hipError_t e = hipMalloc(&B.scratch, need);
-      if (e != hipSuccess) return fail(CS_ENOMEM, "hipMalloc of %zu bytes of batch scratch failed", need);
-      B.scratch_bytes = need;
-      B.last.clear();
-    }
-    if (!B.queue) {
-      hipError_t e = hipMalloc(&B.queue, 256);
-      if (e != hipSuccess) return fail(CS_ENOMEM, "hipMalloc of the batch queue failed");
-    }
-    std::vector<BatchSig> sig(cs_);
-    for (int k = 0; k < cs_; ++k) {
-      const int i = order[k];
-      const Plan& P = *plans[n_host[i]];
-      BatchSig& g = sig[k];
-      std::memset(&g, 0, sizeof g);
-      float2* base = reinterpret_cast<float2*>(static_cast<char*>(B.scratch) + off[k]);
-      g.c = c_cat + off_n_host[i];
-      g.y = y_cat + off_m_host[i];
-      g.x = x_cat + off_n_host[i];
-      g.lam = lambda_dev + i;
-      g.tau = tau_dev + i;
-      g.Y = base;
-      g.chat = base + P.N;
-      g.yhat = base + 2 * P.N + 1;
-      g.tw1 = P.tw1; g.tw2 = P.tw2; g.twlo = P.twlo; g.twhi = P.twhi; g.twk1 = P.twk1; g.twp = P.twp;
-      g.logN = P.logN;
-      g.lo_bits = P.lo_bits;
-    }
-    // descriptors: upload only when they differ from what the device holds
-    const bool same = B.last.size() == sig.size() &&
-                      std::memcmp(B.last.data(), sig.data(), sig.size() * sizeof(BatchSig)) == 0;
-    if (!same) {
-      CS_HIP(hipStreamSynchronize(s));
-      if (B.sigs_cap < sig.size()) {
-        if (B.sigs) CS_HIP(hipFree(B.sigs));
-        B.sigs = nullptr;
-        B.sigs_cap = 0;
-        hipError_t e = hipMalloc(&B.sigs, sig.size() * sizeof(BatchSig));
-        if (e != hipSuccess) return fail(CS_ENOMEM, "hipMalloc of batch descriptors failed");
-        B.sigs_cap = sig.size();
-      }
-      CS_HIP(hipMemcpy(B.sigs, sig.data(), sig.size() * sizeof(BatchSig), hipMemcpyHostToDevice));
-      B.last = sig;
-    }
-    int cus = 0;
-    CS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int per = batch_blocks_dispatch(d / 2);
-    if (per < 1) return fail(CS_EHIP, "batched kernel cannot be resident on this device");
-    const int grid = std::min(cs_, cus * per);
-    if ((st = fill(reinterpret_cast<float*>(B.queue), 1, 0.0f, s)) != CS_OK) return st;
-    BatchSig* dsig = B.sigs;
-    unsigned* q = B.queue;
-    CS_LAUNCH(timed(T_BATCH, s, [&] { return launch_batch_dispatch(d / 2, dsig, cs_, q, iters, grid, s); }));
-  }
-  if (groups.empty()) {
-    g_err.clear();
-    return CS_OK;
-  }
-  // grouped long signals: per-chunk contiguous copies of c, y, lam, tau and
-  // the chunk's spectra, tables and iterates in one grow-only buffer that
-  // the chunks (run one after another on the stream) share. A chunk holds
-  // signals of one length, at most kGroupChunkBytes of scratch (at least one
-  // signal) and at most 65535 signals (grid y).
-  auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
-  auto chunk_bytes = [&](int64_t n, size_t gc) {
-    const int64_t N = n / 2, m = n / d;
-    return up(gc * size_t(N) * 8) + 2 * up(gc * size_t(N + 1) * 8) + 2 * up(gc * size_t(n) * 4) +
-           up(gc * size_t(m) * 4) + 2 * up(gc * 4);
-  };
-  std::vector<GItem> items;
-  size_t gneed = 0;
-  struct GLayout { int64_t n; int first, count; };
-  std::vector<GLayout> lay;
-  for (auto& kv : groups) {
-    const int64_t n = kv.first;
-    const size_t per = chunk_bytes(n, 1);
-    const size_t cap = std::max<size_t>(1, std::min<size_t>(65535, kGroupChunkBytes / per));
-    for (size_t k0 = 0; k0 < kv.second.size(); k0 += cap) {
-      const size_t gc = std::min(cap, kv.second.size() - k0);
-      lay.push_back(GLayout{n, int(items.size()), int(gc)});
-      for (size_t k = k0; k < k0 + gc; ++k) {
-        const int i = kv.second[k];
-        items.push_back(GItem{off_n_host[i], off_m_host[i], i, 0});
-      }
-      gneed = std::max(gneed, chunk_bytes(n, gc));
-    }
-  }
-  if (B.gscratch_bytes < gneed) {
-    CS_HIP(hipStreamSynchronize(s));
-    if (B.gscratch) CS_HIP(hipFree(B.gscratch));
-    B.gscratch = nullptr;
-    B.gscratch_bytes = 0;
-    hipError_t e = hipMalloc(&B.gscratch, gneed);
-    if (e != hipSuccess) return fail(CS_ENOMEM, "hipMalloc of %zu bytes of grouped batch scratch failed", gneed);
-    B.gscratch_bytes = gneed;
-  }
-  // group descriptors: upload only when they differ from what the device holds
-  const bool gsame = B.glast.size() == items.size() &&
-                     std::memcmp(B.glast.data(), items.data(), items.size() * sizeof(GItem)) == 0;
-  if (!gsame) {
-    CS_HIP(hipStreamSynchronize(s));
-    if (B.gitems_cap < items.size()) {
-      if (B.gitems) CS_HIP(hipFree(B.gitems));
-      B.gitems = nullptr;
-      B.gitems_cap = 0;
-      hipError_t e = hipMalloc(&B.gitems, items.size() * sizeof(GItem));
-      if (e != hipSuccess) return fail(CS_ENOMEM, "hipMalloc of grouped batch descriptors failed");
-      B.gitems_cap = items.size();
-    }
-    CS_HIP(hipMemcpy(B.gitems, items.data(), items.size() * sizeof(GItem), hipMemcpyHostToDevice));
-    B.glast = items;
-  }
-  if (!B.gscratch || !B.gitems) return fail(CS_EHIP, "grouped batch buffers missing");
-  for (const GLayout& L : lay) {
-    const Plan& P = *plans[L.n];
-    const int64_t n = L.n, N = n / 2, m = n / d;
-    const size_t gc = size_t(L.count);
-    char* p = static_cast<char*>(B.gscratch);
-    auto take = [&](size_t b) { char* r = p; p += up(b); return r; };
-    float2* Yg = reinterpret_cast<float2*>(take(gc * size_t(N) * 8));
-    float2* chg = reinterpret_cast<float2*>(take(gc * size_t(N + 1) * 8));
-    float2* yhg = reinterpret_cast<float2*>(take(gc * size_t(N + 1) * 8));
-    float* cg = reinterpret_cast<float*>(take(gc * size_t(n) * 4));
-    float* xg = reinterpret_cast<float*>(take(gc * size_t(n) * 4));
-    float* yg = reinterpret_cast<float*>(take(gc * size_t(m) * 4));
-    float* lamg = reinterpret_cast<float*>(take(gc * 4));
-    float* taug = reinterpret_cast<float*>(take(gc * 4));
-    const GItem* it = B.gitems + L.first;
-    const dim3 gg(unsigned(std::min<int64_t>((n + 255) / 256, 512)), unsigned(gc));
-    k_group_gather<<<gg, dim3(256), 0, s>>>(it, n, m, c_cat, y_cat, lambda_dev, tau_dev, cg, yg, lamg, taug);
-    CS_HIP(hipGetLastError());
-    UStride us{};
-    us.Y = N; us.table = N + 1; us.yhat = N + 1; us.chat = N + 1; us.u = n; us.par = 1;
-    const int Bt = int(gc);
-    {
-      UStride u1 = us;
-      u1.in0 = n;
-      PassBArgs b = argsB(P);
-      b.Y = Yg; b.in0 = cg;
-      CS_LAUNCH(launchUB(P, B_FWD_REAL, Bt, b, u1, s));
-      PassAArgs a = argsA(P);
-      a.Y = Yg; a.table = chg; a.chat = chg;
-      UStride u2 = us;
-      u2.chat = 0;
-      CS_LAUNCH(launchUA(P, A_SPEC, Bt, a, u2, s));
-      u1.in0 = m;
-      b.in0 = yg;
-      CS_LAUNCH(launchUB(P, B_FWD_UP, Bt, b, u1, s));
-      a.table = yhg;
-      CS_LAUNCH(launchUA(P, A_SPEC, Bt, a, u2, s));
-    }
-    if ((st = fill(reinterpret_cast<float*>(Yg), gc * size_t(N) * 2, 0.0f, s)) != CS_OK) return st;
-    if ((st = fill(xg, gc * size_t(n), 0.0f, s)) != CS_OK) return st;
-    PassAArgs a = argsA(P);
-    a.Y = Yg; a.chat = chg; a.yhat = yhg; a.tau_dev = taug; a.t = 0;
-    PassBArgs b = argsB(P);
-    b.Y = Yg; b.u = xg; b.tau_dev = taug; b.lam_dev = lamg; b.t = 0;
-    for (int t = 1; t <= iters; ++t) {
-      CS_LAUNCH(launchUA(P, A_ISTA, Bt, a, us, s));
-      b.last = (t == iters);
-      CS_LAUNCH(launchUB(P, B_ISTA, Bt, b, us, s));
-    }
-    k_group_scatter<<<gg, dim3(256), 0, s>>>(it, n, xg, x_cat);
-    CS_HIP(hipGetLastError());
-  }
-  g_err.clear();
-  return CS_OK;
-}
 
 size_t cs_unrolled_ckpt_bytes(int64_t n, int32_t d, int32_t Bt, int32_t K, int32_t every) {
   (void)d;
@@ -1342,6 +1031,7 @@ cs_status cs_check_device(cs_stream stream) {
     snprintf(what, sizeof what, "n=%lld d=%d", (long long)P.n, P.d);
     if ((st = check(P.bar, what)) != CS_OK) return st;
   }
+  if ((st = batch_check_flags(dev)) != CS_OK) return st;
   if (dev >= 0 && dev < kMaxDevices) {
     for (ExtBlock* b : ext_blocks(dev))
       if (b->ptr && b->cleared && (st = check(static_cast<unsigned*>(b->ptr), "caller-provided memory")) != CS_OK)

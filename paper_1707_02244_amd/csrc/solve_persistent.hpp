@@ -89,30 +89,11 @@ struct SolveArgs {
   float rho, inv_rho, d_rho;
 };
 
-// The spectrum buffer Y is the only data workgroups exchange.  It is read
-// and written with relaxed agent-scope atomic accesses: on gfx950 these are
-// plain vector loads/stores carrying the device-coherence bit, so a value
-// stored by one XCD is what another XCD's load returns, without writing back
-// or invalidating any L2 (the read-only c_hat / y_hat tables keep their L2
-// residency across iterations).
-__device__ __forceinline__ float2 ld_coh(const float2* p) {
-  const uint64_t v = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-  return __builtin_bit_cast(float2, v);
-}
-__device__ __forceinline__ void st_coh(float2* p, float2 v) {
-  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), __builtin_bit_cast(uint64_t, v), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // 16-byte forms of ld_coh / st_coh (two adjacent float2) for the register-
 // stage path: raw buffer accesses with the same device-coherence cache bit
 // (sc1) that the relaxed agent-scope atomics above carry.  The buffer
 // resource covers exactly the spectrum buffer, so an offset outside it reads
 // zeros and drops the store instead of touching other memory.
-typedef unsigned cs_u32x4 __attribute__((ext_vector_type(4)));
-constexpr int kCohAux = 16;                  // cache policy: sc1
-constexpr int kBufWord3 = 0x00020000;        // raw 32-bit buffer (gfx9 family)
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t y_rsrc(float2* Y, unsigned n_elems) {
   return __builtin_amdgcn_make_buffer_rsrc(Y, 0, (int)(n_elems * 8u), kBufWord3);
 }

@@ -168,3 +168,51 @@ def test_bad_workspace_rejected():
     # smaller than the smallest plan
     assert lib.cs_set_workspace(ctypes.c_void_p(0x1000), 1024) == _lib.CS_EINVAL
     assert b"smallest" in lib.cs_last_error()
+
+
+def _arr(vals, ctype):
+    a = (ctype * len(vals))(*vals)
+    return ctypes.cast(a, ctypes.c_void_p), a
+
+
+@pytest.mark.parametrize("ns,ds,offs", [
+    ([1 << 9], [4], [0]),                  # n below 2^10
+    ([1 << 19], [4], [0]),                 # n above 2^18
+    ([3000], [4], [0]),                    # not a power of two
+    ([4096], [16], [0]),                   # d outside {2, 4, 8}
+    ([4096], [3], [0]),
+    ([4096, 4096], [4, 4], [0, 1]),        # odd off_n
+    ([4096, 4096], [4, 4], [0, 2048]),     # overlapping n-length slices
+    ([4096], [4], [-2]),                   # negative offset
+])
+def test_batched_bad_layout_rejected(ns, ds, offs):
+    """The batched calls validate the host arrays (sizes, per-signal
+    decimations, offsets, overlap) before any device call."""
+    lib = cs.load()
+    n_p, n_k = _arr(ns, ctypes.c_int64)
+    d_p, d_k = _arr(ds, ctypes.c_int32)
+    o_p, o_k = _arr(offs, ctypes.c_int64)
+    m_p, m_k = _arr([0] * len(ns), ctypes.c_int64)
+    cnt = len(ns)
+    assert lib.cs_ista_solve_batched(cnt, n_p, d_p, o_p, m_p, FAKE, FAKE, FAKE, FAKE, 5, FAKE, NULL) == _lib.CS_EINVAL
+    assert lib.cs_last_error()
+    assert lib.cs_admm_solve_batched(cnt, n_p, d_p, o_p, m_p, FAKE, FAKE, FAKE, FAKE, 5, 0,
+                                     FAKE, FAKE, FAKE, NULL) == _lib.CS_EINVAL
+
+
+def test_batched_null_and_count_checks():
+    lib = cs.load()
+    n_p, n_k = _arr([4096], ctypes.c_int64)
+    d_p, d_k = _arr([4], ctypes.c_int32)
+    o_p, o_k = _arr([0], ctypes.c_int64)
+    assert lib.cs_ista_solve_batched(-1, n_p, d_p, o_p, o_p, FAKE, FAKE, FAKE, FAKE, 5, FAKE, NULL) == _lib.CS_EINVAL
+    assert lib.cs_ista_solve_batched(1, n_p, NULL, o_p, o_p, FAKE, FAKE, FAKE, FAKE, 5, FAKE, NULL) == _lib.CS_EINVAL
+    assert lib.cs_ista_solve_batched(1, n_p, d_p, o_p, o_p, FAKE, FAKE, FAKE, FAKE, -1, FAKE, NULL) == _lib.CS_EINVAL
+    assert lib.cs_ista_solve_batched(1, n_p, d_p, o_p, o_p, FAKE, FAKE, NULL, FAKE, 5, FAKE, NULL) == _lib.CS_EINVAL
+    assert lib.cs_admm_solve_batched(1, n_p, d_p, o_p, o_p, FAKE, FAKE, FAKE, FAKE, 5, 0,
+                                     FAKE, NULL, FAKE, NULL) == _lib.CS_EINVAL
+    # count = 0 is a no-op, whatever the pointers
+    assert lib.cs_ista_solve_batched(0, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, 5, NULL, NULL) == _lib.CS_OK
+    assert lib.cs_admm_solve_batched(0, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, 5, 1,
+                                     NULL, NULL, NULL, NULL) == _lib.CS_OK
+    assert lib.cs_batched_schedule(None, 0) == _lib.CS_EINVAL

@@ -87,7 +87,7 @@ def test_batched_zero_iterations_and_empty():
     got = run_batch(probs, 4, 0)
     assert all(np.all(a == 0.0) for a in got)
     # count = 0 with null pointers is a no-op
-    cs.load().cs_ista_solve_batched(0, None, 4, None, None, None, None, None, None, 5, None, None)
+    cs.load().cs_ista_solve_batched(0, None, None, None, None, None, None, None, None, 5, None, None)
 
 
 def test_batched_repeat_and_change():
@@ -158,3 +158,124 @@ def test_batched_full_workload_sampled():
         worst = max(worst, e)
         assert e <= IT_TOL, (i, ns[i], e)
     print("full uneven batch, %d sampled signals, worst rel err at t=%d: %.3e" % (len(pick), T, worst))
+
+
+# ----------------------------------------------------------------------------
+# per-signal decimation, batched ADMM, the schedule report
+# ----------------------------------------------------------------------------
+def mixed_d(specs, seed):
+    """specs: list of (n, d); one draw per signal."""
+    rng = np.random.default_rng(seed)
+    sigs = [workloads.signal(int(n), int(d), max(2, int(n) // 256), int(rng.integers(1 << 30))) for n, d in specs]
+    return batched.build_batch(sigs)
+
+
+def split(xs, ns):
+    off_n, _ = cs.batch_offsets(ns, 4)
+    return [xs[o:o + n] for o, n in zip(off_n, ns)]
+
+
+SPECS = [(1 << 12, 2), (1 << 15, 8), (1 << 10, 4), (1 << 17, 4), (1 << 13, 8), (1 << 16, 2), (1 << 11, 2),
+         (1 << 18, 8), (1 << 14, 4), (1 << 12, 8)]
+
+
+def test_batched_per_signal_decimation_vs_oracle():
+    """Signals with different decimations in one call, each against its own
+    oracle solve."""
+    probs = mixed_d(SPECS, 91)
+    ns, c, y, lam, tau = batched.concat(probs)
+    ds = np.array([p.d for p in probs], np.int32)
+    T = 40
+    xs = h(cs.ista_solve_batched(ns, ds, g(c), g(y), g(lam), g(tau), T))
+    ref = batched.ista_batched(probs, T)
+    worst = 0.0
+    for i, (a, b) in enumerate(zip(split(xs, ns), ref)):
+        e = rel(a, b)
+        worst = max(worst, e)
+        assert e <= IT_TOL, (i, SPECS[i], e)
+    print("per-signal d batch: worst rel err at t=%d: %.3e" % (T, worst))
+
+
+def admm_batch(probs, rhos, T, warm_from=None):
+    ns, c, y, lam, _ = batched.concat(probs)
+    ds = np.array([p.d for p in probs], np.int32)
+    kw = {}
+    if warm_from is not None:
+        kw = dict(z_cat=g(warm_from[0]), u_cat=g(warm_from[1]), warm=True)
+    x, z, u = cs.admm_solve_batched(ns, ds, g(c), g(y), g(lam), g(np.asarray(rhos, np.float32)), T, **kw)
+    return ns, h(x), h(z), h(u)
+
+
+def test_batched_admm_vs_oracle():
+    """Batched ADMM with per-signal rho and d: x, z, u of every signal
+    against the oracle's ADMM (Alg. 2) at t = 60."""
+    probs = mixed_d(SPECS, 92)
+    rhos = [1.0, 0.5, 2.0, 1.0, 1.0, 0.25, 1.0, 1.0, 4.0, 1.0]
+    T = 60
+    ns, x, z, u = admm_batch(probs, rhos, T)
+    ref = batched.admm_batched(probs, rhos, T)
+    worst = 0.0
+    for i, (a, b, cc, r) in enumerate(zip(split(x, ns), split(z, ns), split(u, ns), ref)):
+        ex, ez = rel(a, r[0]), rel(b, r[1])
+        eu = rel(cc, r[2]) if np.linalg.norm(r[2]) > 0 else float(np.abs(cc).max())
+        worst = max(worst, ex, ez, eu)
+        assert ex <= IT_TOL and ez <= IT_TOL and eu <= IT_TOL, (i, SPECS[i], ex, ez, eu)
+    print("batched ADMM: worst x/z/u rel err at t=%d: %.3e" % (T, worst))
+
+
+def test_batched_admm_warm_start_continues():
+    """T1 cold iterations, then T2 warm iterations from the returned (z, u),
+    equal T1 + T2 cold iterations."""
+    probs = mixed_d(SPECS[:6], 93)
+    rhos = [1.0] * 6
+    ns, x1, z1, u1 = admm_batch(probs, rhos, 15)
+    _, x2, z2, u2 = admm_batch(probs, rhos, 10, warm_from=(z1, u1))
+    _, x3, z3, u3 = admm_batch(probs, rhos, 25)
+    for a, b in ((x2, x3), (z2, z3), (u2, u3)):
+        assert rel(a, b) <= 1e-6
+
+
+def test_batched_admm_zero_iterations():
+    probs = mixed_d(SPECS[:3], 94)
+    ns, x, z, u = admm_batch(probs, [1.0] * 3, 0)
+    assert not x.any() and not z.any() and not u.any()
+    zw = np.full(len(x), 0.5)
+    uw = np.full(len(x), -0.25)
+    _, x, z, u = admm_batch(probs, [1.0] * 3, 0, warm_from=(zw, uw))
+    assert np.all(z == 0.5) and np.all(u == -0.25)
+
+
+def test_batched_schedule_report():
+    """After a batched call the library reports its schedule: one grid that
+    fits on the device, the tuner's trials, and whether a graph replay ran."""
+    probs = mixed_d(SPECS, 95)
+    ns, c, y, lam, tau = batched.concat(probs)
+    ds = np.array([p.d for p in probs], np.int32)
+    cs.ista_solve_batched(ns, ds, g(c), g(y), g(lam), g(tau), 5)
+    torch.cuda.synchronize()
+    info = cs.batched_schedule()
+    print("batched schedule:", info)
+    assert info["grid"] >= 1 and info["wg_per_cu"] >= 1
+    assert isinstance(info["trials"], list) and len(info["trials"]) >= 1
+    assert isinstance(info["graph"], bool)
+
+
+def test_batched_admm_full_workload_sampled():
+    """The 512-signal uneven batch through batched ADMM (rho = 1, 100
+    iterations): the first signal of each length and the last signal against
+    the oracle's ADMM."""
+    sigs = workloads.uneven_batch()
+    probs = batched.build_batch(sigs, workloads.UNEVEN_PARAMS["lam_frac"])
+    T = 100
+    rhos = [1.0] * len(probs)
+    ns, x, z, u = admm_batch(probs, rhos, T)
+    xs, zs = split(x, ns), split(z, ns)
+    nl = [p.n for p in probs]
+    pick = sorted({nl.index(n) for n in set(nl)} | {len(nl) - 1})
+    worst = 0.0
+    for i in pick:
+        r = batched.admm_one(probs[i], 1.0, T)
+        ex, ez = rel(xs[i], r[0]), rel(zs[i], r[1])
+        worst = max(worst, ex, ez)
+        assert ex <= IT_TOL and ez <= IT_TOL, (i, nl[i], ex, ez)
+    print("full uneven batch ADMM, %d sampled signals, worst rel err at t=%d: %.3e" % (len(pick), T, worst))
