@@ -253,6 +253,22 @@ cs_status cs2_admm_solve(const float* s, const float* h, int32_t rows, int32_t c
 size_t cs_workspace_bytes(int64_t n, int32_t d, int32_t mode);
 cs_status cs_set_workspace(void* ws, size_t bytes);
 
+/* Allocation-free ISTA, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, arithmetic and results as cs_ista_solve with
+ * obj == NULL, for n <= 2^20 (larger n: CS_EINVAL, nothing enqueued).  The
+ * plan block (spectrum buffer, c_hat / y_hat tables, twiddles, barrier area;
+ * cs_workspace_bytes(2^20, d, 1) = 12.1 MiB) is a static device array of the
+ * library, one copy per GPU, held until the process ends; the call itself
+ * makes no device allocation.  The array keeps the last call's contents (the
+ * library rewrites what a call needs: twiddles when n changes, the barrier
+ * counters every call).  All calls on one GPU share the array: calls that
+ * overlap on one GPU (other streams, other threads) race; serialise them.
+ * The first call on a device looks the array's device address up with
+ * hipGetSymbolAddress (CS_EHIP if that fails).  */
+cs_status cs_ista_solve_noalloc(const float* c, int64_t n, int32_t d, const float* y, float lambda, float tau,
+                                int32_t iters, float* x, cs_stream stream);
+
 /* Solver schedule.  For 2^8 <= n <= 2^22 a solve runs as ONE cooperative
  * launch: all iterations in a persistent kernel whose workgroups keep the
  * time-domain state in registers and meet at a grid barrier between the row

@@ -17,7 +17,7 @@ CS_OK, CS_EINVAL, CS_ENOMEM, CS_EHIP, CS_ENOTSUP = 0, -1, -2, -3, -4
 _NAMES = {CS_EINVAL: "CS_EINVAL", CS_ENOMEM: "CS_ENOMEM", CS_EHIP: "CS_EHIP", CS_ENOTSUP: "CS_ENOTSUP"}
 
 EXPORTS = ["cs_circ_apply", "cs_circ_apply_T", "cs_circ_apply_direct", "cs_circ_apply_T_direct", "cs_circ_norm_bound", "cs_ista_solve",
-           "cs_admm_solve", "cs_ista_solve_batched", "cs_admm_solve_batched", "cs_batched_schedule",
+           "cs_admm_solve", "cs_ista_solve_noalloc", "cs_ista_solve_batched", "cs_admm_solve_batched", "cs_batched_schedule",
            "cs_unrolled_ckpt_bytes", "cs_unrolled_ista_fwd",
            "cs_unrolled_ista_bwd", "cs2_apply", "cs2_apply_T", "cs2_norm_bound", "cs2_ista_solve",
            "cs2_admm_solve", "cs_workspace_bytes", "cs_set_workspace", "cs_set_solver_path", "cs_check_device",
@@ -52,6 +52,7 @@ def load():
         "cs_circ_norm_bound": [P, I64, P, P],
         "cs_ista_solve": [P, I64, I32, P, F, F, I32, P, P, P],
         "cs_admm_solve": [P, I64, I32, P, F, F, I32, I32, P, P, P, P, P],
+        "cs_ista_solve_noalloc": [P, I64, I32, P, F, F, I32, P, P],
         "cs_ista_solve_batched": [I32, P, P, P, P, P, P, P, P, I32, P, P],
         "cs_admm_solve_batched": [I32, P, P, P, P, P, P, P, P, I32, I32, P, P, P, P],
         "cs_batched_schedule": [ctypes.c_char_p, ctypes.c_size_t],
@@ -168,6 +169,15 @@ def ista_solve(c, d, y, lam, tau, iters, x=None, obj=None):
         x = torch.empty(n, device=c.device, dtype=torch.float32)
     _check(load().cs_ista_solve(_ptr(c, "c"), n, d, _ptr(y, "y", n // d), float(lam), float(tau),
                                 int(iters), _ptr(x, "x", n), _ptr(obj, "obj", iters), _stream(c)))
+    return x
+
+
+def ista_solve_noalloc(c, d, y, lam, tau, iters, x):
+    """ISTA through the allocation-free entry point (n <= 2^20); x is the
+    caller's output tensor (nothing is allocated here either)."""
+    n = c.numel()
+    _check(load().cs_ista_solve_noalloc(_ptr(c, "c"), n, d, _ptr(y, "y", n // d), float(lam), float(tau),
+                                        int(iters), _ptr(x, "x", n), _stream(c)))
     return x
 
 

@@ -452,12 +452,34 @@ cs_status bind_external(int dev, int64_t n, int d, ExtBlock& blk, hipStream_t s,
   return CS_OK;
 }
 
+// Allocation-free ISTA (cs_ista_solve_noalloc): its plan block is the
+// file-scope device array `scratch`, sized for the largest supported n.  The
+// array's name is a host-side stand-in in host code; its device address is
+// taken once per device with hipGetSymbolAddress (with that device current)
+// and kept in g_noalloc[dev].ptr, which is what every kernel receives.
+constexpr int64_t kNoAllocMaxN = int64_t(1) << 20;
+constexpr int64_t up64c(int64_t v) { return (v + 63) & ~int64_t(63); }
+constexpr int ilog2cc(int64_t v) { return v <= 1 ? 0 : 1 + ilog2cc(v / 2); }
+// float2 words of the (n, d) plan block: the layout of plan_layout
+constexpr int64_t layout_words(int64_t n) {
+  const int64_t N = n / 2;
+  const int pN = ilog2cc(N);
+  const int64_t N1 = (pN % 2) ? (int64_t(1) << ((pN - 1) / 2)) : (int64_t(1) << (pN / 2 - 1));
+  const int64_t N2 = N / N1;
+  const int lo = (pN + 1) / 2;
+  return up64c(kBarWords / 2) + 64 + up64c(N1) + up64c(N2) + up64c(int64_t(1) << lo) + up64c(N >> lo) +
+         up64c(N1) + up64c(N2) + up64c(N) + 2 * up64c(N + 1);
+}
+constexpr int64_t kNoAllocWords = layout_words(kNoAllocMaxN);
+static __device__ __align__(256) float2 scratch[kNoAllocWords];
+ExtBlock g_noalloc[kMaxDevices];
+
 // The plan a single-signal call runs on: bound to the device's workspace if
 // the caller has set one, else the library's cached plan.  `cached` (may be
 // null) receives the library plan when one is used (it owns the objective
 // buffer).
 // The external blocks of a device whose error flags cs_check_device reads.
-std::vector<ExtBlock*> ext_blocks(int dev) { return {&g_ws[dev]}; }
+std::vector<ExtBlock*> ext_blocks(int dev) { return {&g_ws[dev], &g_noalloc[dev]}; }
 
 cs_status plan_for_call(int64_t n, int d, hipStream_t s, Plan& view, Plan** cached) {
   int dev = 0;
@@ -1172,6 +1194,45 @@ cs_status cs_ista_solve(const float* c, int64_t n, int32_t d, const float* y, fl
   Plan V;
   if ((st = plan_for_call(n, d, s, V, nullptr)) != CS_OK) return st;
   if ((st = ista_run(V, c, y, lambda, tau, iters, x, obj, s, true)) != CS_OK) return st;
+  g_err.clear();
+  return CS_OK;
+}
+
+cs_status cs_ista_solve_noalloc(const float* c, int64_t n, int32_t d, const float* y, float lambda, float tau,
+                                int32_t iters, float* x, cs_stream stream) {
+  cs_status st = check_ista(c, n, d, y, lambda, tau, iters, x);
+  if (st != CS_OK) return st;
+  if (n > kNoAllocMaxN)
+    return fail(CS_EINVAL, "n=%lld exceeds the allocation-free limit n <= %lld", (long long)n,
+                (long long)kNoAllocMaxN);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (iters == 0) {
+    if ((st = fill(x, size_t(n), 0.0f, s)) != CS_OK) return st;
+    g_err.clear();
+    return CS_OK;
+  }
+  int dev = 0;
+  CS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CS_ENOTSUP, "device %d beyond the supported %d", dev, kMaxDevices);
+  Plan V;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    ExtBlock& blk = g_noalloc[dev];
+    if (!blk.ptr) {
+      // once per device, with that device current: the device address of
+      // this device's copy of `scratch`
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr)
+        return fail(CS_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+      blk.ptr = ptr;
+      blk.bytes = sizeof(scratch);
+      blk.tables_n = 0;
+      blk.cleared = false;
+    }
+    if ((st = bind_external(dev, n, d, blk, s, V)) != CS_OK) return st;
+  }
+  if ((st = ista_run(V, c, y, lambda, tau, iters, x, nullptr, s, false)) != CS_OK) return st;
   g_err.clear();
   return CS_OK;
 }
