@@ -253,6 +253,33 @@ cs_status cs2_admm_solve(const float* s, const float* h, int32_t rows, int32_t c
 size_t cs_workspace_bytes(int64_t n, int32_t d, int32_t mode);
 cs_status cs_set_workspace(void* ws, size_t bytes);
 
+/* Circulant ADMM with an arbitrary row set (Section 4.3, Alg. 3).  A = P C
+ * with C the circulant of first column c (n, device) and P keeping the m rows
+ * listed in omega_host (a HOST array of m distinct indices in [0, n), any
+ * order); y (m, device) holds the measurements in omega's order.  The split
+ *     min 1/2 ||y - P v||^2 + alpha ||z||_1   s.t.  v = C x,  z = x
+ * is solved from x = v = z = mu = nu = 0 with, per iteration,
+ *     x  = (rho C^T C + sigma I)^-1 (rho C^T (v + mu) + sigma (z - nu))
+ *     v  = (P^T P + rho I)^-1 (rho C x - rho mu + P^T y)
+ *     z  = eta_{alpha/sigma}(x + nu)          (soft threshold, Eq. 4)
+ *     mu = mu + tau (v - C x),   nu = nu + tau (x - z)
+ * (the updates of the section's augmented Lagrangian; the printed algorithm's
+ * "v = v + mu" is read as forming v + mu for the x-update, and one step tau
+ * serves both multipliers).  The circulant inverse and C x are applied in the
+ * Fourier domain, the diagonal (P^T P + rho I)^-1 in the time domain.
+ * Outputs x, v, z, mu, nu (n each, device) after `iters` iterations (all
+ * zero for iters == 0).  Requires n a power of two in [2^8, 2^22], 1 <= m <=
+ * n, alpha >= 0, rho > 0, sigma > 0, tau > 0 (the section quotes tau <
+ * (1 + sqrt 5)/2 for convergence), iters >= 0; CS_EINVAL otherwise,
+ * including a repeated or out-of-range index in omega.  Uses the (n, d = 2)
+ * plan of the single-signal calls (its two spectrum buffers and c_hat
+ * table).  During the solve v holds P^T y and z the indicator of omega, and
+ * omega's indices are copied through x: the call synchronises the stream
+ * once, after that copy.  Two launches per iteration.  */
+cs_status cs_cpadmm_solve(const float* c, int64_t n, const int64_t* omega_host, int64_t m, const float* y,
+                          float alpha, float rho, float sigma, float tau, int32_t iters, float* x, float* v,
+                          float* z, float* mu, float* nu, cs_stream stream);
+
 /* Allocation-free ISTA, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  Same arguments, arithmetic and results as cs_ista_solve with

@@ -62,7 +62,7 @@ def d_diag(omega, n, rho):
     return dd
 
 
-def _iterate(Cop, CTop, Bop, omega, y, alpha, rho, sigma, tau, iters, record):
+def _iterate(Cop, CTop, Bop, omega, y, alpha, rho, sigma, tau, iters, record, callback=None):
     n = Cop.n
     py = scatter(omega, y, n)
     dd = d_diag(omega, n, rho)
@@ -81,6 +81,8 @@ def _iterate(Cop, CTop, Bop, omega, y, alpha, rho, sigma, tau, iters, record):
         nu = nu + tau * (x - z)
         if record:
             hist.append((t, x.copy(), v.copy(), z.copy(), mu.copy(), nu.copy()))
+        if callback is not None:
+            callback(t, x, v, z, mu, nu)
     out = (x, v, z, mu, nu)
     return (out, hist) if record else out
 
@@ -102,11 +104,11 @@ class _Dense:
         return scipy.linalg.cho_solve(self.fac, q)
 
 
-def dense_cpadmm(c, omega, y, alpha, rho, sigma, tau, iters, record=False):
+def dense_cpadmm(c, omega, y, alpha, rho, sigma, tau, iters, record=False, callback=None):
     """Alg. 3 with explicit C and a Cholesky factor of rho C^T C + sigma I
     (n up to a few thousand).  Returns (x, v, z, mu, nu) after `iters`."""
     op = _Dense(np.asarray(c, np.float64), rho, sigma)
-    return _iterate(op, op.T, op.B, omega, y, alpha, rho, sigma, tau, iters, record)
+    return _iterate(op, op.T, op.B, omega, y, alpha, rho, sigma, tau, iters, record, callback)
 
 
 class _FFT:
@@ -126,15 +128,27 @@ class _FFT:
         return np.fft.irfft(self.binv * np.fft.rfft(q), self.n)
 
 
-def fft_cpadmm(c, omega, y, alpha, rho, sigma, tau, iters, record=False):
+def fft_cpadmm(c, omega, y, alpha, rho, sigma, tau, iters, record=False, callback=None):
     """Alg. 3 with C, C^T and B applied through the FFT (any n)."""
     op = _FFT(c, rho, sigma)
-    return _iterate(op, op.T, op.B, omega, y, alpha, rho, sigma, tau, iters, record)
+    return _iterate(op, op.T, op.B, omega, y, alpha, rho, sigma, tau, iters, record, callback)
 
 
 def dense_A(c, omega):
     """A = P C for the rows in Omega (in the order given)."""
     return dense.dense_C(c)[np.asarray(omega)]
+
+
+def problem(sig, omega, alpha_frac):
+    """The rounded problem of a random-row draw: y = P C x* in FP64 rounded
+    to float32, alpha = alpha_frac max |A^T y| in FP64 on the rounded y,
+    rounded to float32 (the same rule as the decimating problem)."""
+    c = np.asarray(sig.c, np.float64)
+    op = _FFT(c, 1.0, 1.0)
+    y = op(np.asarray(sig.x_true, np.float64))[np.asarray(omega)].astype(np.float32)
+    aty = op.T(scatter(omega, y.astype(np.float64), len(c)))
+    alpha = np.float32(alpha_frac * float(np.max(np.abs(aty))))
+    return y, alpha
 
 
 def objective(c, omega, y, alpha, x):

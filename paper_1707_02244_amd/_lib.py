@@ -17,7 +17,7 @@ CS_OK, CS_EINVAL, CS_ENOMEM, CS_EHIP, CS_ENOTSUP = 0, -1, -2, -3, -4
 _NAMES = {CS_EINVAL: "CS_EINVAL", CS_ENOMEM: "CS_ENOMEM", CS_EHIP: "CS_EHIP", CS_ENOTSUP: "CS_ENOTSUP"}
 
 EXPORTS = ["cs_circ_apply", "cs_circ_apply_T", "cs_circ_apply_direct", "cs_circ_apply_T_direct", "cs_circ_norm_bound", "cs_ista_solve",
-           "cs_admm_solve", "cs_ista_solve_noalloc", "cs_ista_solve_batched", "cs_admm_solve_batched", "cs_batched_schedule",
+           "cs_admm_solve", "cs_cpadmm_solve", "cs_ista_solve_noalloc", "cs_ista_solve_batched", "cs_admm_solve_batched", "cs_batched_schedule",
            "cs_unrolled_ckpt_bytes", "cs_unrolled_ista_fwd",
            "cs_unrolled_ista_bwd", "cs2_apply", "cs2_apply_T", "cs2_norm_bound", "cs2_ista_solve",
            "cs2_admm_solve", "cs_workspace_bytes", "cs_set_workspace", "cs_set_solver_path", "cs_check_device",
@@ -53,6 +53,7 @@ def load():
         "cs_ista_solve": [P, I64, I32, P, F, F, I32, P, P, P],
         "cs_admm_solve": [P, I64, I32, P, F, F, I32, I32, P, P, P, P, P],
         "cs_ista_solve_noalloc": [P, I64, I32, P, F, F, I32, P, P],
+        "cs_cpadmm_solve": [P, I64, P, I64, P, F, F, F, F, I32, P, P, P, P, P, P],
         "cs_ista_solve_batched": [I32, P, P, P, P, P, P, P, P, I32, P, P],
         "cs_admm_solve_batched": [I32, P, P, P, P, P, P, P, P, I32, I32, P, P, P, P],
         "cs_batched_schedule": [ctypes.c_char_p, ctypes.c_size_t],
@@ -179,6 +180,21 @@ def ista_solve_noalloc(c, d, y, lam, tau, iters, x):
     _check(load().cs_ista_solve_noalloc(_ptr(c, "c"), n, d, _ptr(y, "y", n // d), float(lam), float(tau),
                                         int(iters), _ptr(x, "x", n), _stream(c)))
     return x
+
+
+def cpadmm_solve(c, omega, y, alpha, rho, sigma, tau, iters):
+    """Circulant ADMM with the arbitrary row set `omega` (host integer array,
+    distinct indices; y in omega's order); returns (x, v, z, mu, nu)."""
+    import numpy as np
+    import torch
+    n = c.numel()
+    om = np.ascontiguousarray(omega, dtype=np.int64)
+    out = [torch.empty(n, device=c.device, dtype=torch.float32) for _ in range(5)]
+    _check(load().cs_cpadmm_solve(_ptr(c, "c"), n, ctypes.c_void_p(om.ctypes.data), len(om),
+                                  _ptr(y, "y", len(om)), float(alpha), float(rho), float(sigma), float(tau),
+                                  int(iters), *[_ptr(t, nm, n) for t, nm in zip(out, ("x", "v", "z", "mu", "nu"))],
+                                  _stream(c)))
+    return tuple(out)
 
 
 def admm_solve(c, d, y, lam, rho, iters, x=None, z=None, u=None, warm=False, obj=None):

@@ -1,6 +1,7 @@
 // Pass-A instantiation for one row length N2 = CS_LEN.
 #include "launch.hpp"
 #include "unrolled.hpp"
+#include "cpadmm.hpp"
 
 #ifndef CS_LEN
 #error "compile with -DCS_LEN=<row length>"
@@ -55,6 +56,16 @@ hipError_t launch_urow<CS_LEN>(int op, int d2, int grid, int batch, const PassAA
   }
 #undef CS_U
   return hipGetLastError();
+}
+
+template <>
+hipError_t launch_cp_row<CS_LEN>(int grid, const CpArgs& a, hipStream_t s) {
+  if constexpr (CS_LEN <= kCpMaxN2) {
+    k_cp_row<CS_LEN, kThreads><<<dim3(grid), dim3(kThreads), 0, s>>>(a);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace cs

@@ -1,6 +1,7 @@
 // Pass-B instantiation for one column length N1 = CS_LEN.
 #include "launch.hpp"
 #include "unrolled.hpp"
+#include "cpadmm.hpp"
 
 #ifndef CS_LEN
 #error "compile with -DCS_LEN=<column length>"
@@ -42,6 +43,18 @@ hipError_t launch_ucol<CS_LEN>(int mode, int grid, int batch, const PassBArgs& a
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <>
+hipError_t launch_cp_col<CS_LEN>(int last, int grid, const CpArgs& a, hipStream_t s) {
+  if constexpr (CS_LEN <= kCpMaxN1) {
+    constexpr int CB = cp_cb(CS_LEN);
+    if (last) k_cp_col<CS_LEN, CB, kThreads, true><<<dim3(grid), dim3(kThreads), 0, s>>>(a);
+    else k_cp_col<CS_LEN, CB, kThreads, false><<<dim3(grid), dim3(kThreads), 0, s>>>(a);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace cs

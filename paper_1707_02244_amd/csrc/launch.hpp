@@ -13,6 +13,14 @@ hipError_t launch_passA(int op, int d2, int grid, const PassAArgs& a, hipStream_
 template <int N1>
 hipError_t launch_passB(int mode, int grid, const PassBArgs& a, hipStream_t s);
 
+struct CpArgs;
+// circulant ADMM with an arbitrary row set (cpadmm.hpp): row pass over row
+// pairs, column pass over column blocks (last: write the outputs)
+template <int N2>
+hipError_t launch_cp_row(int grid, const CpArgs& a, hipStream_t s);
+template <int N1>
+hipError_t launch_cp_col(int last, int grid, const CpArgs& a, hipStream_t s);
+
 struct UStride;
 // batched (grid y = signal) row / column passes for the unrolled solver
 template <int N2>

@@ -61,7 +61,7 @@ cs_status batch_check_flags(int dev);
 // Timed launch kinds (names as reported by cs_timing_read).
 enum TimedKind {
   T_A_ISTA = 0, T_B_ISTA, T_A_ADMM, T_B_ADMM, T_S_ISTA, T_S_ADMM, T_BATCH,
-  T_C2_ISTA, T_R2_ISTA, T_C2_ADMM, T_R2_ADMM, T_DIRECT, T_DIRECT_T, T_COUNT
+  T_C2_ISTA, T_R2_ISTA, T_C2_ADMM, T_R2_ADMM, T_DIRECT, T_DIRECT_T, T_CP_ROW, T_CP_COL, T_COUNT
 };
 bool timing_on();
 // Records the start (tok == -1 on entry) or the stop event of a launch.

@@ -24,6 +24,7 @@
 #include "launch.hpp"
 #include "solve_persistent.hpp"
 #include "unrolled.hpp"
+#include "cpadmm.hpp"
 
 #include <algorithm>
 #include <numeric>
@@ -138,9 +139,9 @@ std::vector<TimedLaunch> g_timed;
 std::vector<TimedLaunch> g_open;
 std::vector<hipEvent_t> g_event_pool;
 const char* kTimedNames[T_COUNT] = {"passA_ista", "passB_ista", "passA_admm", "passB_admm",
-                                    "solve_ista", "solve_admm", "batch_ista",
+                                    "solve_ista", "solve_admm", "batched",
                                     "col2_ista", "row2_ista", "col2_admm", "row2_admm", "direct",
-                                    "direct_T"};
+                                    "direct_T", "cp_row", "cp_col"};
 
 hipEvent_t take_event() {
   if (!g_event_pool.empty()) {
@@ -184,6 +185,7 @@ using namespace rt;
 
 constexpr int64_t kMinN = 256;
 constexpr int64_t kMaxN = int64_t(1) << 25;
+constexpr int64_t kCpMaxN = int64_t(1) << 22;   // circulant ADMM with an arbitrary row set
 constexpr int kMinLogNPersistent = 7;    // N = n/2 = 2^7 .. 2^21: one cooperative launch per solve
 constexpr int kMaxLogNPersistent = 21;
 
@@ -515,6 +517,48 @@ hipError_t launchA(const Plan& P, int op, const PassAArgs& a, hipStream_t s) {
     case 4096: return launch_passA<4096>(op, d2, grid, a, s);
     case 8192: return launch_passA<8192>(op, d2, grid, a, s);
     default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launchCpRow(const Plan& P, const CpArgs& a, hipStream_t s) {
+  const int grid = P.N1 / 2;
+  switch (P.N2) {
+    case 16: return launch_cp_row<16>(grid, a, s);
+    case 32: return launch_cp_row<32>(grid, a, s);
+    case 64: return launch_cp_row<64>(grid, a, s);
+    case 128: return launch_cp_row<128>(grid, a, s);
+    case 256: return launch_cp_row<256>(grid, a, s);
+    case 512: return launch_cp_row<512>(grid, a, s);
+    case 1024: return launch_cp_row<1024>(grid, a, s);
+    case 2048: return launch_cp_row<2048>(grid, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launchCpCol(const Plan& P, int last, const CpArgs& a, hipStream_t s) {
+  const int grid = P.N2 / cp_cb(P.N1);
+  switch (P.N1) {
+    case 8: return launch_cp_col<8>(last, grid, a, s);
+    case 16: return launch_cp_col<16>(last, grid, a, s);
+    case 32: return launch_cp_col<32>(last, grid, a, s);
+    case 64: return launch_cp_col<64>(last, grid, a, s);
+    case 128: return launch_cp_col<128>(last, grid, a, s);
+    case 256: return launch_cp_col<256>(last, grid, a, s);
+    case 512: return launch_cp_col<512>(last, grid, a, s);
+    case 1024: return launch_cp_col<1024>(last, grid, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// P^T y into v (zero elsewhere) and the indicator of Omega into z, for the
+// circulant ADMM with an arbitrary row set; omega is read from `idx` (int32,
+// validated on the host).  v and z are zeroed first by the caller.
+__global__ void k_cp_scatter(const int* __restrict__ idx, int64_t m, const float* __restrict__ y,
+                             float* __restrict__ v, float* __restrict__ z) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < m; i += int64_t(gridDim.x) * blockDim.x) {
+    const int j = idx[i];
+    v[j] = y[i];
+    z[j] = 1.0f;
   }
 }
 
@@ -1233,6 +1277,88 @@ cs_status cs_ista_solve_noalloc(const float* c, int64_t n, int32_t d, const floa
     if ((st = bind_external(dev, n, d, blk, s, V)) != CS_OK) return st;
   }
   if ((st = ista_run(V, c, y, lambda, tau, iters, x, nullptr, s, false)) != CS_OK) return st;
+  g_err.clear();
+  return CS_OK;
+}
+
+cs_status cs_cpadmm_solve(const float* c, int64_t n, const int64_t* omega_host, int64_t m, const float* y,
+                          float alpha, float rho, float sigma, float tau, int32_t iters, float* x, float* v,
+                          float* z, float* mu, float* nu, cs_stream stream) {
+  if (!c || !y || !x || !v || !z || !mu || !nu) return fail(CS_EINVAL, "a device array is NULL");
+  if (!is_pow2(n) || n < kMinN || n > kCpMaxN)
+    return fail(CS_EINVAL, "n=%lld must be a power of two in [%lld, %lld]", (long long)n, (long long)kMinN,
+                (long long)kCpMaxN);
+  if (m < 1 || m > n) return fail(CS_EINVAL, "m=%lld must be in [1, n]", (long long)m);
+  if (!omega_host) return fail(CS_EINVAL, "omega is NULL");
+  if (!finite(alpha) || alpha < 0.0f) return fail(CS_EINVAL, "alpha=%g must be finite and >= 0", alpha);
+  if (!finite(rho) || rho <= 0.0f) return fail(CS_EINVAL, "rho=%g must be finite and > 0", rho);
+  if (!finite(sigma) || sigma <= 0.0f) return fail(CS_EINVAL, "sigma=%g must be finite and > 0", sigma);
+  if (!finite(tau) || tau <= 0.0f) return fail(CS_EINVAL, "tau=%g must be finite and > 0", tau);
+  if (iters < 0) return fail(CS_EINVAL, "iters=%d must be >= 0", iters);
+  // Omega: distinct indices in [0, n), in any order
+  std::vector<int> idx(static_cast<size_t>(m));
+  {
+    std::vector<int64_t> sorted(omega_host, omega_host + m);
+    std::sort(sorted.begin(), sorted.end());
+    if (sorted.front() < 0 || sorted.back() >= n)
+      return fail(CS_EINVAL, "omega holds an index outside [0, n)");
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+      return fail(CS_EINVAL, "omega holds a repeated index");
+    for (int64_t i = 0; i < m; ++i) idx[size_t(i)] = int(omega_host[i]);
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  cs_status st = CS_OK;
+  for (float* p : {x, v, z, mu, nu})
+    if ((st = fill(p, size_t(n), 0.0f, s)) != CS_OK) return st;
+  if (iters == 0) {
+    g_err.clear();
+    return CS_OK;
+  }
+  Plan V;
+  if ((st = plan_for_call(n, 2, s, V, nullptr)) != CS_OK) return st;
+  if ((st = setup_chat(V, c, s)) != CS_OK) return st;
+  // Omega's indices go to the device through the caller's x array (n floats
+  // >= m ints), which the solve writes only at its end; the copy is waited
+  // for before the host vector goes away.
+  int* didx = reinterpret_cast<int*>(x);
+  CS_HIP(hipMemcpyAsync(didx, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  k_cp_scatter<<<dim3(unsigned(std::min<int64_t>((m + 255) / 256, 1024))), dim3(256), 0, s>>>(didx, m, y, v, z);
+  CS_HIP(hipGetLastError());
+  CS_HIP(hipStreamSynchronize(s));
+  // a = v + mu = 0 and b = z - nu = 0 at the start (x = v = z = mu = nu = 0)
+  float2* Yb = V.yhat;   // the plan's second spectrum buffer
+  if ((st = fill(reinterpret_cast<float*>(V.Y), size_t(V.N) * 2, 0.0f, s)) != CS_OK) return st;
+  if ((st = fill(reinterpret_cast<float*>(Yb), size_t(V.N) * 2, 0.0f, s)) != CS_OK) return st;
+  CpArgs a{};
+  a.Ya = V.Y;
+  a.Yb = Yb;
+  a.chat = V.chat;
+  a.twk1 = V.twk1;
+  a.twp = V.twp;
+  a.twlo = V.twlo;
+  a.twhi = V.twhi;
+  a.tw1 = V.tw1;
+  a.tw2 = V.tw2;
+  a.lo_bits = V.lo_bits;
+  a.N1 = V.N1;
+  a.N2 = V.N2;
+  a.N = V.N;
+  a.inv_n = 1.0f / float(n);
+  a.rho = rho;
+  a.sigma = sigma;
+  a.tau = tau;
+  a.thr = alpha / sigma;
+  a.d_in = 1.0f / (1.0f + rho);
+  a.d_out = 1.0f / rho;
+  a.mu = mu;
+  a.nu = nu;
+  a.v = v;
+  a.z = z;
+  a.x = x;
+  for (int t = 1; t <= iters; ++t) {
+    CS_LAUNCH(timed(T_CP_ROW, s, [&] { return launchCpRow(V, a, s); }));
+    CS_LAUNCH(timed(T_CP_COL, s, [&] { return launchCpCol(V, t == iters, a, s); }));
+  }
   g_err.clear();
   return CS_OK;
 }

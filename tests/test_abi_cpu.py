@@ -216,3 +216,38 @@ def test_batched_null_and_count_checks():
     assert lib.cs_admm_solve_batched(0, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, 5, 1,
                                      NULL, NULL, NULL, NULL) == _lib.CS_OK
     assert lib.cs_batched_schedule(None, 0) == _lib.CS_EINVAL
+
+
+@pytest.mark.parametrize("n,omega,alpha,rho,sigma,tau,iters", [
+    (1000, [0, 1], 0.1, 1.0, 1.0, 1.0, 5),           # n not a power of two
+    (1 << 23, [0, 1], 0.1, 1.0, 1.0, 1.0, 5),        # n above 2^22
+    (4096, [0, 4096], 0.1, 1.0, 1.0, 1.0, 5),        # index out of range
+    (4096, [-1, 3], 0.1, 1.0, 1.0, 1.0, 5),
+    (4096, [7, 3, 7], 0.1, 1.0, 1.0, 1.0, 5),        # repeated index
+    (4096, [1, 2], -0.1, 1.0, 1.0, 1.0, 5),          # alpha < 0
+    (4096, [1, 2], 0.1, 0.0, 1.0, 1.0, 5),           # rho <= 0
+    (4096, [1, 2], 0.1, 1.0, -1.0, 1.0, 5),          # sigma <= 0
+    (4096, [1, 2], 0.1, 1.0, 1.0, 0.0, 5),           # tau <= 0
+    (4096, [1, 2], 0.1, 1.0, 1.0, 1.0, -1),          # iters < 0
+])
+def test_cpadmm_bad_arguments_rejected(n, omega, alpha, rho, sigma, tau, iters):
+    """The circulant ADMM with a row set validates sizes, the index set and
+    the scalars on the host before any device call."""
+    lib = cs.load()
+    om = (ctypes.c_int64 * len(omega))(*omega)
+    st = lib.cs_cpadmm_solve(FAKE, n, ctypes.cast(om, ctypes.c_void_p), len(omega), FAKE, alpha, rho, sigma, tau,
+                             iters, FAKE, FAKE, FAKE, FAKE, FAKE, NULL)
+    assert st == _lib.CS_EINVAL
+    assert lib.cs_last_error()
+
+
+def test_cpadmm_null_and_count_rejected():
+    lib = cs.load()
+    om = (ctypes.c_int64 * 2)(1, 2)
+    omp = ctypes.cast(om, ctypes.c_void_p)
+    assert lib.cs_cpadmm_solve(FAKE, 4096, NULL, 2, FAKE, 0.1, 1.0, 1.0, 1.0, 5, FAKE, FAKE, FAKE, FAKE, FAKE,
+                               NULL) == _lib.CS_EINVAL
+    assert lib.cs_cpadmm_solve(FAKE, 4096, omp, 0, FAKE, 0.1, 1.0, 1.0, 1.0, 5, FAKE, FAKE, FAKE, FAKE, FAKE,
+                               NULL) == _lib.CS_EINVAL
+    assert lib.cs_cpadmm_solve(FAKE, 4096, omp, 2, FAKE, 0.1, 1.0, 1.0, 1.0, 5, FAKE, NULL, FAKE, FAKE, FAKE,
+                               NULL) == _lib.CS_EINVAL
