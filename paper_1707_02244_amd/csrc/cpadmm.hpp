@@ -164,27 +164,26 @@ __global__ __launch_bounds__(T) void k_cp_col(CpArgs a) {
     j2 = j2_0 + (r % CB);
     j = (size_t)k1 * N2 + j2;
   };
-  {
-    float2 v[EPT];
+  // loads in chunks of CH per thread (all of a chunk in flight at once)
+  constexpr int CH = EPT < 8 ? EPT : 8;
+#pragma unroll 1
+  for (int k0 = 0; k0 < EPT; k0 += CH) {
+    float2 v[CH], t[CH];
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-      const int e = tid + k * T;
+    for (int k = 0; k < CH; ++k) {
+      const int e = tid + (k0 + k) * T;
       if (FULL || e < NE) {
         int s, j2, k1;
         size_t j;
         gaddr(e, s, j, j2, k1);
         v[k] = (s ? a.Yb : a.Ya)[j];
+        t[k] = cp_twN(a, j2 * k1);
       }
     }
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-      const int e = tid + k * T;
-      if (FULL || e < NE) {
-        int s, j2, k1;
-        size_t j;
-        gaddr(e, s, j, j2, k1);
-        lds[lp(e)] = cmulc(v[k], cp_twN(a, j2 * k1));
-      }
+    for (int k = 0; k < CH; ++k) {
+      const int e = tid + (k0 + k) * T;
+      if (FULL || e < NE) lds[lp(e)] = cmulc(v[k], t[k]);
     }
   }
   __syncthreads();
@@ -194,6 +193,7 @@ __global__ __launch_bounds__(T) void k_cp_col(CpArgs a) {
   float2* nu = reinterpret_cast<float2*>(a.nu);
   float2* vv = reinterpret_cast<float2*>(a.v);
   float2* zz = reinterpret_cast<float2*>(a.z);
+#pragma unroll 2
   for (int q = tid; q < N1 * CB; q += T) {
     const int i = q / CB, c = q % CB;
     const size_t j = (size_t)i * N2 + j2_0 + c;
@@ -225,14 +225,28 @@ __global__ __launch_bounds__(T) void k_cp_col(CpArgs a) {
   if constexpr (!LAST) {
     __syncthreads();
     lds_fft<N1, S, T, false, true, N1>(lds, tws, tid);
+#pragma unroll 1
+    for (int k0 = 0; k0 < EPT; k0 += CH) {
+      float2 t[CH];
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-      const int e = tid + k * T;
-      if (FULL || e < NE) {
-        int s, j2, k1;
-        size_t j;
-        gaddr(e, s, j, j2, k1);
-        (s ? a.Yb : a.Ya)[j] = cmul(lds[lp(e)], cp_twN(a, j2 * k1));
+      for (int k = 0; k < CH; ++k) {
+        const int e = tid + (k0 + k) * T;
+        if (FULL || e < NE) {
+          int s, j2, k1;
+          size_t j;
+          gaddr(e, s, j, j2, k1);
+          t[k] = cp_twN(a, j2 * k1);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int e = tid + (k0 + k) * T;
+        if (FULL || e < NE) {
+          int s, j2, k1;
+          size_t j;
+          gaddr(e, s, j, j2, k1);
+          (s ? a.Yb : a.Ya)[j] = cmul(lds[lp(e)], t[k]);
+        }
       }
     }
   }
