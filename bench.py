@@ -104,6 +104,7 @@ def main():
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-deblur1d", action="store_true")
     ap.add_argument("--no-cpadmm", action="store_true")
+    ap.add_argument("--no-recovery", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain copy kernel (read and write this many MiB, 3 launches): the "
                          "known-size reference that scales profiler byte counters")
@@ -239,6 +240,9 @@ def main():
     if not args.no_cpadmm:
         progress("circulant ADMM, random rows: n=2^22, m=n/2")
         out["cpadmm_random_rows"] = bench_cpadmm(cs, torch, dev, args.steps, args.warmup)
+    if not args.no_recovery:
+        progress("recovery time to MSE 1e-4 at n=2^15")
+        out["recovery"] = bench_recovery(cs, torch, dev)
 
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib << 18, device=dev)
@@ -252,6 +256,9 @@ def main():
     if not args.no_cpu_baseline:
         progress("cpu baseline: FP64 oracle sample")
         out["cpu_baseline"] = cpu_baseline(sig, prm, tau, lam)
+        if not args.no_recovery:
+            progress("cpu baseline: FP64 oracle MSE curves at n=2^15")
+            out["cpu_baseline"]["recovery_curves"] = cpu_recovery_curves()
     progress("done")
     print(json.dumps(out), flush=True)
 
@@ -453,6 +460,65 @@ def bench_cpadmm(cs, torch, dev, steps, warmup):
             "mse_z_vs_truth": err / n}
 
 
+def bench_recovery(cs, torch, dev):
+    """Recovery time and MSE over time (Section 6): n = 2^15, m = n/2, k =
+    n/10, MSE = ||x* - x||^2 / n, target 1e-4.  ISTA (tau = 0.1) and ADMM
+    (rho = 0.1) keep every other row (d = 2); the circulant ADMM of Section
+    4.3 (rho = sigma = 0.1, multiplier step 1) takes m = n/2 random rows.
+    lambda = 1e-4.  Each checkpoint is a solve from zero of that many
+    iterations, timed with HIP events (set-up included, as the paper's
+    recovery time includes ADMM's inversions); the MSE is of x (ISTA) or z
+    (ADMM).  y comes from the library's operator (random rows: numpy FFT on the
+    host, input preparation)."""
+    import numpy as np
+    import workloads
+    prm = workloads.RECOVERY_PARAMS
+    sig = workloads.recovery_signal()
+    c = torch.from_numpy(sig.c).to(dev)
+    xs = torch.from_numpy(sig.x_true).to(dev)
+    y = cs.circ_apply(c, sig.d, xs)
+    n = sig.n
+    out = torch.empty(n, device=dev)
+    x3 = [torch.empty(n, device=dev) for _ in range(3)]
+
+    def timed_ms(f):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = f()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), r
+
+    def curve(run, checkpoints, truth):
+        run(1)   # plan and tables outside the curve
+        torch.cuda.synchronize()
+        pts = []
+        for t in checkpoints:
+            ms, est = timed_ms(lambda: run(t))
+            mse = float(((est - truth) ** 2).mean().item())
+            pts.append({"iters": t, "gpu_ms": ms, "mse": mse})
+        hit = next((p for p in pts if p["mse"] <= prm["target_mse"]), None)
+        return {"points": pts, "recovered_at_iters": hit["iters"] if hit else None,
+                "recovery_ms": hit["gpu_ms"] if hit else None,
+                "final_mse": pts[-1]["mse"]}
+
+    res = {"workload": "n=2^15, m=n/2, k=n/10 N(0,1), c ~ N(0,1/m), lambda=1e-4; ISTA tau=0.1, ADMM rho=0.1 (d=2); "
+                       "circulant ADMM (random rows) rho=sigma=0.1, multiplier step 1; target MSE 1e-4",
+           "target_mse": prm["target_mse"]}
+    res["ista"] = curve(lambda t: cs.ista_solve(c, sig.d, y, prm["lam"], prm["ista_tau"], t, x=out),
+                        prm["ista_checkpoints"], xs)
+    res["admm"] = curve(lambda t: cs.admm_solve(c, sig.d, y, prm["lam"], prm["rho"], t, x=x3[0], z=x3[1],
+                                                u=x3[2])[1], prm["admm_checkpoints"], xs)
+    sig2, omega = workloads.recovery_random_rows()
+    c64 = sig2.c.astype(np.float64)
+    y2 = np.fft.irfft(np.fft.rfft(c64) * np.fft.rfft(sig2.x_true.astype(np.float64)), n)[omega].astype(np.float32)
+    c2_, y2g, xs2 = (torch.from_numpy(a).to(dev) for a in (sig2.c, y2, sig2.x_true))
+    res["cpadmm"] = curve(lambda t: cs.cpadmm_solve(c2_, omega, y2g, prm["lam"], prm["rho"], prm["sigma"],
+                                                    prm["cp_tau"], t)[2], prm["cpadmm_checkpoints"], xs2)
+    cs.check_device()
+    return res
+
+
 def copy_bandwidth(torch, dev):
     """GB/s of a plain elementwise copy-like kernel (read 1 GiB, write 1 GiB),
     larger than the Infinity Cache so it streams from HBM."""
@@ -606,6 +672,36 @@ def cpu_baseline(sig, prm, tau, lam):
             "sample": "FP64 FFT reference at n=2^22: %d ISTA + %d ADMM iterations "
                       "(%.3f s and %.3f s per iteration), rate for the 300:100 mix; "
                       "host has %d usable cores" % (ki, ka, ti, ta, len(os.sched_getaffinity(0)))}
+
+
+def cpu_recovery_curves():
+    """The FP64 oracle's MSE over its own wall time on the recovery-time
+    workload (n = 2^15, same parameters as the GPU curves, y from the oracle's
+    operator): ADMM to 1200 iterations (past the target), ISTA to 2000; numpy's
+    FFT, one thread per transform."""
+    import workloads
+    from oracle import fftref, problem
+    prm = workloads.RECOVERY_PARAMS
+    sig = workloads.recovery_signal()
+    pr = problem.build(sig, 0.01)
+    op = pr.op()
+    y = pr.y.astype(np.float64)
+    xs = sig.x_true.astype(np.float64)
+    marks = {1, 10, 100, 200, 500, 1000, 1100, 1200, 2000}
+    out = {}
+    for name, iters in (("admm", 1200), ("ista", 2000)):
+        pts, t0 = [], time.perf_counter()
+
+        def cb(t, x, *rest):
+            est = rest[0] if name == "admm" else x
+            if t in marks:
+                pts.append({"iters": t, "cpu_s": time.perf_counter() - t0, "mse": float(((est - xs) ** 2).mean())})
+        if name == "admm":
+            fftref.admm(op, y, prm["lam"], prm["rho"], iters, callback=cb)
+        else:
+            fftref.ista(op, y, prm["lam"], prm["ista_tau"], iters, callback=cb)
+        out[name] = pts
+    return out
 
 
 if __name__ == "__main__":

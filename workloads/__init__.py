@@ -206,3 +206,33 @@ def random_rows_large(seed_offset: int = 0):
 
 
 RANDOM_ROWS_PARAMS = dict(alpha_frac=0.01, rho=1.0, sigma=1.0, tau=1.0, iters=100)
+
+
+def recovery_signal(seed_offset: int = 0):
+    """The recovery-time study of Section 6 (MSE over time at n = 2^15):
+    m = n/2 (every other row, d = 2), k = n/10 N(0,1) nonzeros, c ~ N(0, 1/m).
+    Same draw order as draw_1d."""
+    n = 1 << 15
+    return draw_1d(np.random.default_rng(SEED_BASE + 8 + seed_offset), n, 2, n // 10)
+
+
+def recovery_random_rows(seed_offset: int = 0):
+    """The same study with m = n/2 rows drawn at random (the paper's sampling),
+    for the circulant ADMM of Section 4.3."""
+    n = 1 << 15
+    return random_rows_signal(n, n // 2, n // 10, SEED_BASE + 9 + seed_offset)
+
+
+# Section 6 sets alpha = 1e-4 and sigma = tau = 0.1 with an MSE target of
+# 1e-4.  Read here as: lambda = alpha (absolute), the ISTA step tau = 0.1
+# (below 2 / ||A||^2 for these draws), rho = sigma = 0.1 for ADMM (Alg. 2) and
+# the circulant ADMM (Alg. 3), whose multiplier step is 1 (inside the quoted
+# convergence range (0, (1 + sqrt 5)/2)).  Checkpoints: iteration counts at
+# which the MSE is measured (each a solve from zero).
+RECOVERY_PARAMS = dict(
+    lam=1e-4, ista_tau=0.1, rho=0.1, sigma=0.1, cp_tau=1.0, target_mse=1e-4,
+    ista_checkpoints=[1, 2, 5, 10, 20, 50, 100, 200, 500, 1000, 2000, 5000, 10000, 20000, 40000, 60000, 80000,
+                      100000, 120000, 150000],
+    admm_checkpoints=[1, 2, 5, 10, 20, 50, 100, 200, 500, 800, 1000, 1100, 1200, 1500, 2000, 3000],
+    cpadmm_checkpoints=[1, 2, 5, 10, 20, 50, 100, 200, 500, 1000, 2000, 2500, 3000, 4000, 5000],
+)
