@@ -65,10 +65,14 @@ constexpr int kPBColPts = CS_PB_COL_PTS;
 constexpr int pb_min(int a, int b) { return a < b ? a : b; }
 constexpr int pb_max(int a, int b) { return a > b ? a : b; }
 constexpr int pb_ai(int L) { return pb_max(1, pb_min(pb_n1(L) / 2, kPBRowPts / (2 * pb_n2(L)))); }
-constexpr int pb_cbw(int L) { return pb_max(kColsPerBlock, pb_min(pb_n2(L), kPBColPts / pb_n1(L))); }
+// (the largest length, N1 = 256, takes 16 columns rather than 8: 128-byte
+// runs of the spectrum and the iterate instead of 64-byte ones)
+constexpr int pb_cbw(int L) {
+  return L == kPBMaxLogN ? 16 : pb_max(kColsPerBlock, pb_min(pb_n2(L), kPBColPts / pb_n1(L)));
+}
 // LDS of one item: 2 AI rows of N2 (+ padding) or N1 x CBW interleaved
 constexpr int kPBRowLds = lds_rows(kPBRowPts + 2 * kPBMaxN1 * kPadA);
-constexpr int kPBColLds = lds_padded(pb_max(kPBColPts, kPBMaxN1 * kColsPerBlock));
+constexpr int kPBColLds = lds_padded(pb_max(kPBColPts, kPBMaxN1 * 16));
 constexpr int kPBLds = pb_max(kPBRowLds, kPBColLds);
 // LDS copy of the four-step twiddles W_N^e (two levels) of the largest length
 constexpr int kPBMaxTwN = (1 << ((kPBMaxLogN + 1) / 2)) + (1 << (kPBMaxLogN - (kPBMaxLogN + 1) / 2));

@@ -521,9 +521,9 @@ __device__ __forceinline__ void adj_partials(const PassBArgs& a, double s_th, do
   __syncthreads();
 }
 
-// COH (persistent launches): device-coherent spectrum and state accesses, the
-// whole column block loaded at once, and the state (B_ISTA / B_ADMM) loaded
-// together with the spectrum instead of after the inverse transform.  TWL:
+// COH (persistent launches): device-coherent spectrum and state accesses, and
+// (up to 8 values per thread) the state of B_ISTA / B_ADMM loaded together
+// with the spectrum instead of after the inverse transform.  TWL:
 // the four-step twiddles come from an LDS copy twn = [W_N^e, e < 2^lo_bits |
 // W_N^(e 2^lo_bits), e < N >> lo_bits] instead of the global tables.
 template <int N1, int MODE, int T, bool COH = false, int CBW = kColsPerBlock, bool TWL = false>
@@ -533,7 +533,7 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
   constexpr int CB = CBW;   // adjacent columns held, interleaved
   constexpr int NE = N1 * CB;
   constexpr int EPT = (NE + T - 1) / T;
-  constexpr int CH = COH ? EPT : (EPT < 8 ? EPT : 8);
+  constexpr int CH = EPT < 8 ? EPT : 8;
   constexpr bool FULL = (NE % T) == 0;
   const int j2_0 = blk * CB;
   const int N2 = a.N2;
@@ -541,7 +541,7 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
   constexpr bool HAS_INV = (MODE == B_ISTA || MODE == B_ADMM || MODE == B_OUT_ALL || MODE == B_OUT_DEC ||
                             MODE == B_ISTA_REC || MODE == B_ADJ_X || MODE == B_ADJ_XV);
   constexpr bool STATE = (MODE == B_ISTA || MODE == B_ADMM || MODE == B_ISTA_REC);
-  constexpr bool PRE = COH && STATE;   // state loaded with the spectrum
+  constexpr bool PRE = COH && STATE && EPT <= 8;   // state loaded with the spectrum (when it fits)
   auto twN = [&](int e) -> float2 {
     if constexpr (TWL) {
       e &= (a.N - 1);
