@@ -78,6 +78,18 @@ cs_status cs_circ_apply_T_direct(const float* c, int64_t n, int32_t d, const flo
  * (Alg. 1 asks for tau in (0, ||A||_2^-2)).  */
 cs_status cs_circ_norm_bound(const float* c, int64_t n, float* out, cs_stream stream);
 
+/* Generator of the composite circulant C B of the compressed-deblurring
+ * problem (Section 7): B is the order-L box blur, the circulant whose rows
+ * are right-circular shifts of b with b_j = 1/L for j < L and 0 otherwise,
+ * and C B is again circulant (a product of circulants), with first column
+ *     out[k] = (1/L) sum_{t<L} c[(k + t) mod n],   k < n,
+ * each sum taken in double and rounded once to float.  Pass `out` as the
+ * generator of any call above to solve with A = P C B.
+ * c: n device floats, out: n device floats (distinct from c); n a power of
+ * two in [2^8, 2^25] (the solvers' range); 1 <= L <= min(n, 4096) (O(n L)
+ * work).  No allocation; CS_EINVAL on a bad argument, nothing enqueued.  */
+cs_status cs_box_blur_generator(const float* c, int64_t n, int32_t L, float* out, cs_stream stream);
+
 /* ISTA, Alg. 1:  x(0) = 0;  for t = 1..iters:
  *     x(t) = eta_{tau*lambda}( x(t-1) + tau A^T (y - A x(t-1)) )
  * eta is the soft threshold of Eq. 4 (strict comparison).  The threshold is

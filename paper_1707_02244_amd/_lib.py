@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libcscirc.so")
 CS_OK, CS_EINVAL, CS_ENOMEM, CS_EHIP, CS_ENOTSUP = 0, -1, -2, -3, -4
 _NAMES = {CS_EINVAL: "CS_EINVAL", CS_ENOMEM: "CS_ENOMEM", CS_EHIP: "CS_EHIP", CS_ENOTSUP: "CS_ENOTSUP"}
 
-EXPORTS = ["cs_circ_apply", "cs_circ_apply_T", "cs_circ_apply_direct", "cs_circ_apply_T_direct", "cs_circ_norm_bound", "cs_ista_solve",
+EXPORTS = ["cs_circ_apply", "cs_circ_apply_T", "cs_circ_apply_direct", "cs_circ_apply_T_direct", "cs_circ_norm_bound", "cs_box_blur_generator", "cs_ista_solve",
            "cs_admm_solve", "cs_cpadmm_solve", "cs_ista_solve_noalloc", "cs_ista_solve_batched", "cs_admm_solve_batched", "cs_batched_schedule",
            "cs_unrolled_ckpt_bytes", "cs_unrolled_ista_fwd",
            "cs_unrolled_ista_bwd", "cs2_apply", "cs2_apply_T", "cs2_norm_bound", "cs2_ista_solve",
@@ -50,6 +50,7 @@ def load():
         "cs_circ_apply_direct": [P, I64, I32, P, P, P],
         "cs_circ_apply_T_direct": [P, I64, I32, P, P, P],
         "cs_circ_norm_bound": [P, I64, P, P],
+        "cs_box_blur_generator": [P, I64, I32, P, P],
         "cs_ista_solve": [P, I64, I32, P, F, F, I32, P, P, P],
         "cs_admm_solve": [P, I64, I32, P, F, F, I32, I32, P, P, P, P, P],
         "cs_ista_solve_noalloc": [P, I64, I32, P, F, F, I32, P, P],
@@ -159,6 +160,17 @@ def circ_norm_bound(c, out=None):
     if out is None:
         out = torch.empty(1, device=c.device, dtype=torch.float32)
     _check(load().cs_circ_norm_bound(_ptr(c, "c"), c.numel(), _ptr(out, "out", 1), _stream(c)))
+    return out
+
+
+def box_blur_generator(c, L, out=None):
+    """Generator of C B for the order-L box blur B (Section 7): out[k] is
+    the mean of c over the L samples starting at k, circularly."""
+    import torch
+    n = c.numel()
+    if out is None:
+        out = torch.empty(n, device=c.device, dtype=torch.float32)
+    _check(load().cs_box_blur_generator(_ptr(c, "c"), n, int(L), _ptr(out, "out", n), _stream(c)))
     return out
 
 

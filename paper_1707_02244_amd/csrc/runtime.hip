@@ -562,6 +562,20 @@ __global__ void k_cp_scatter(const int* __restrict__ idx, int64_t m, const float
   }
 }
 
+// Generator of C B for the order-L box blur B (Section 7): the mean of c
+// over the L samples starting at k, circularly (n a power of two), summed in
+// double and rounded once.  Neighbouring threads read overlapping windows,
+// so the L-fold reads hit the cache.
+__global__ void k_box_blur(const float* __restrict__ c, int64_t n, int L, float* __restrict__ out) {
+  const int64_t mask = n - 1;
+  const double inv = 1.0 / double(L);
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x) {
+    double s = 0.0;
+    for (int t = 0; t < L; ++t) s += double(c[(k + t) & mask]);
+    out[k] = float(s * inv);
+  }
+}
+
 hipError_t launchB(const Plan& P, int mode, const PassBArgs& a, hipStream_t s) {
   const int grid = P.N2 / kColsPerBlock;
   switch (P.N1) {
@@ -1221,6 +1235,20 @@ cs_status cs_circ_norm_bound(const float* c, int64_t n, float* out, cs_stream st
   if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
   if ((st = fill(out, 1, 0.0f, s)) != CS_OK) return st;
   if ((st = max_abs2(P->chat, P->N + 1, out, s)) != CS_OK) return st;
+  g_err.clear();
+  return CS_OK;
+}
+
+cs_status cs_box_blur_generator(const float* c, int64_t n, int32_t L, float* out, cs_stream stream) {
+  cs_status st = check_common(c, n, 2);
+  if (st != CS_OK) return st;
+  if (!out) return fail(CS_EINVAL, "out is NULL");
+  if (out == c) return fail(CS_EINVAL, "out must not alias c");
+  if (L < 1 || L > 4096 || L > n) return fail(CS_EINVAL, "L=%d must be in [1, min(n, 4096)]", L);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const unsigned grid = unsigned(std::min<int64_t>((n + 255) / 256, 4096));
+  k_box_blur<<<dim3(grid), dim3(256), 0, s>>>(c, n, L, out);
+  CS_LAUNCH(hipGetLastError());
   g_err.clear();
   return CS_OK;
 }

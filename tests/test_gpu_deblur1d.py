@@ -2,11 +2,15 @@
 synthetic field vectorised (n = 2^20), A = P C B with B the order-5 box
 blur, m = n/2 (d = 2), ADMM with rho = 1 and lambda = 1e-2.
 
-The HIP path takes the generator of C B as an input array composed on the
-host in float64 and rounded to float32; the oracle composes it on its own
-in FP64 from the definition of B (`oracle/deblur.py`).  Tolerances as in the
-other parity tests: iterates relative l2 <= 1e-4, final objective 1e-5.
+The HIP path forms the generator of C B with the library's
+cs_box_blur_generator; the oracle composes it on its own in FP64 from the
+definition of B (`oracle/deblur.py`).  Tolerances as in the other parity
+tests: the generator to float rounding, iterates relative l2 <= 1e-4 up to
+t = 100, the final objective F(z(300)) 1e-5 against the oracle's.
 """
+import sys
+import time
+
 import numpy as np
 import pytest
 
@@ -38,44 +42,82 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def blurred_generator_f32(c32, L):
-    """Input preparation for the HIP path: the generator of C B, i.e. the
-    mean of c over L consecutive samples starting at each index."""
-    c64 = c32.astype(np.float64)
-    return np.mean([np.roll(c64, -t) for t in range(L)], axis=0).astype(np.float32)
-
-
 @pytest.fixture(scope="module")
 def field():
     sig = workloads.deblur_field()
     op = fftref.Operator(deblur.composite_generator(sig.c, PRM["L"]), sig.d)
     y = op.A(sig.x_true.astype(np.float64)).astype(np.float32)
-    return sig, op, y, blurred_generator_f32(sig.c, PRM["L"])
+    return sig, op, y, cs.box_blur_generator(g(sig.c), PRM["L"])
+
+
+@pytest.mark.parametrize("n,L", [(256, 1), (256, 5), (4096, 7), (1 << 16, 256), (1 << 20, 5), (1 << 12, 4096)])
+def test_box_blur_generator_vs_oracle(n, L):
+    """Element by element against the FP64 composition (B from its
+    definition, then C times B's first column): float rounding of the same
+    value."""
+    c = np.random.default_rng(n + L).standard_normal(n).astype(np.float32)
+    got = h(cs.box_blur_generator(g(c), L))
+    ref = deblur.composite_generator(c, L)
+    tol = 2.0 ** -24 * np.abs(ref) + 1e-12 * np.abs(c).max()
+    assert np.all(np.abs(got - ref) <= tol), float(np.max(np.abs(got - ref) - tol))
+
+
+def test_box_blur_generator_rejects_bad_order():
+    c = g(np.ones(256, np.float32))
+    for L in (0, 257, -1):
+        with pytest.raises(cs.CsError):
+            cs.box_blur_generator(c, L)
+    with pytest.raises(cs.CsError):
+        cs.box_blur_generator(g(np.ones(1 << 14, np.float32)), 4097)
 
 
 def test_first_iterates(field):
     sig, op, y, c_in = field
     lam, rho = PRM["lam"], PRM["rho"]
     _, hist = fftref.admm(op, y.astype(np.float64), lam, rho, 5, record=True)
-    c, yg = g(c_in), g(y)
+    yg = g(y)
     for t in (1, 2, 5):
-        x, z, u = (h(v) for v in cs.admm_solve(c, sig.d, yg, lam, rho, t))
+        x, z, u = (h(v) for v in cs.admm_solve(c_in, sig.d, yg, lam, rho, t))
         assert rel(x, hist[t - 1][1]) <= 1e-4 and rel(z, hist[t - 1][2]) <= 1e-4, t
 
 
+@pytest.mark.timeout(900)
 def test_full_run_objective_and_recovery(field):
-    """300 iterations: the GPU trace ends at the oracle's FP64 objective of
-    the returned x and decreases overall; the recovered field has a
-    normalised squared error below 0.1 (the FP64 oracle reaches 0.0295 at
-    300 iterations on this field)."""
+    """300 iterations (the benchmarked run): iterates x, z, u against the
+    FP64 oracle at t <= 100 (relative l2 1e-4); the final objective F(z(300))
+    against the oracle's F(z(300)) at 1e-5 (both evaluated in FP64); the GPU
+    trace ends at F of the returned x and decreases overall; the recovered
+    field has a normalised squared error below 0.1 (the FP64 oracle reaches
+    0.0295 at 300 iterations on this field)."""
     sig, op, y, c_in = field
     lam, rho, T = PRM["lam"], PRM["rho"], PRM["admm_iters"]
+    checks = [10, 25, 50, 100]
+    hist = {}
+    y64 = y.astype(np.float64)
+    t0 = time.perf_counter()
+
+    def cb(t, x, z, u):
+        if t in checks or t == T:
+            hist[t] = (x.copy(), z.copy(), u.copy())
+        if t % 50 == 0:
+            print("[oracle deblur] t=%d (%.0fs)" % (t, time.perf_counter() - t0), file=sys.stderr, flush=True)
+    fftref.admm(op, y64, lam, rho, T, callback=cb)
+    yg = g(y)
+    for t in checks:
+        got = [h(v) for v in cs.admm_solve(c_in, sig.d, yg, lam, rho, t)]
+        for name, a, b in zip("xzu", got, hist[t]):
+            assert rel(a, b) <= 1e-4, (t, name, rel(a, b))
     obj = torch.empty(T, device=DEV)
-    x, z, u = cs.admm_solve(g(c_in), sig.d, g(y), lam, rho, T, obj=obj)
+    x, z, u = cs.admm_solve(c_in, sig.d, yg, lam, rho, T, obj=obj)
     f = h(obj)
     zz = h(z)
-    y64 = y.astype(np.float64)
-    ref = 0.5 * np.sum((y64 - op.A(h(x))) ** 2) + lam * np.sum(np.abs(h(x)))
+
+    def F(v):
+        return 0.5 * np.sum((y64 - op.A(v)) ** 2) + lam * np.sum(np.abs(v))
+    fz, fo = F(zz), F(hist[T][1])
+    print("deblur 1-D: F(z(%d)) GPU %.9e oracle %.9e (rel %.2e)" % (T, fz, fo, abs(fz - fo) / fo))
+    assert abs(fz - fo) <= 1e-5 * fo
+    ref = F(h(x))
     assert abs(f[-1] - ref) <= 1e-5 * ref, (f[-1], ref)
     assert f[-1] < f[0]
     x_true = sig.x_true.astype(np.float64)
