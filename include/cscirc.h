@@ -99,8 +99,10 @@ cs_status cs_box_blur_generator(const float* c, int64_t n, int32_t L, float* out
  * objective of Eq. 3 (halved) along the iterates,
  *     obj[t-1] = F(x(t)) = 1/2 ||y - A x(t)||^2 + lambda ||x(t)||_1,
  * the residual taken by Parseval from the m-point spectrum the iteration
- * already forms and summed in double per workgroup.  A trace runs the
- * two-pass schedule (one row and one column launch per iteration).
+ * already forms and summed in double per workgroup.  A trace keeps the
+ * schedule an untraced call takes (the persistent single launch where it
+ * applies, see cs_set_solver_path); the iterates are the same with or
+ * without it.
  * Requires lambda >= 0, tau > 0, iters >= 0.  */
 cs_status cs_ista_solve(const float* c, int64_t n, int32_t d, const float* y, float lambda,
                         float tau, int32_t iters, float* x, float* obj, cs_stream stream);
@@ -118,7 +120,7 @@ cs_status cs_ista_solve(const float* c, int64_t n, int32_t d, const float* y, fl
  * obj: NULL, or a device array of `iters` floats that receives
  *     obj[t-1] = F(x(t)) = 1/2 ||y - A x(t)||^2 + lambda ||x(t)||_1
  * for the x-update iterate (Eq. 3 halved; the same Parseval residual as
- * ISTA's).  A trace runs the two-pass schedule.
+ * ISTA's), on the same schedule as an untraced call.
  * Requires lambda >= 0, rho > 0, iters >= 0.  */
 cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, float lambda,
                         float rho, int32_t iters, int32_t warm, float* x, float* z, float* u,

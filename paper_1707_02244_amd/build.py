@@ -59,6 +59,8 @@ def build(jobs: int | None = None, verbose: bool = False, incremental: bool = Fa
         units.append((os.path.join(CSRC, "inst_passB.hip"), os.path.join(BUILD, "passB_%d.o" % L), ["-DCS_LEN=%d" % L]))
     for L in SOLVE_LOGN:
         units.append((os.path.join(CSRC, "inst_solve.hip"), os.path.join(BUILD, "solve_%d.o" % L), ["-DCS_LOGN=%d" % L]))
+        units.append((os.path.join(CSRC, "inst_solve.hip"), os.path.join(BUILD, "solve_tr_%d.o" % L),
+                      ["-DCS_LOGN=%d" % L, "-DCS_TRACE=1"]))
     for A in BATCH_ALG:
         units.append((os.path.join(CSRC, "inst_bpersist.hip"), os.path.join(BUILD, "bpersist_%d.o" % A), ["-DCS_ALG=%d" % A]))
     for L in COL2_LENGTHS:

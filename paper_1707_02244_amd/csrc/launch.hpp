@@ -30,10 +30,11 @@ template <int N1>
 hipError_t launch_ucol(int mode, int grid, int batch, const PassBArgs& a, const UStride& st, hipStream_t s);
 
 struct SolveArgs;
-// persistent solver for N = 2^LOGN complex points (inst_solve.hip)
-template <int LOGN>
+// persistent solver for N = 2^LOGN complex points (inst_solve.hip); TR: the
+// instance that also writes the objective trace's partial sums
+template <int LOGN, bool TR>
 hipError_t launch_solve(int alg, int d2, const SolveArgs& a, hipStream_t s);
-template <int LOGN>
+template <int LOGN, bool TR>
 int solve_blocks_per_cu(int alg, int d2);
 
 // persistent batched solver, ALG 0: ISTA, 1: ADMM (inst_bpersist.hip): the

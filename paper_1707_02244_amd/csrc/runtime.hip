@@ -213,7 +213,7 @@ struct Plan {
   int64_t n = 0;
   int d = 0;
   int N = 0, N1 = 0, N2 = 0, M = 0, lo_bits = 0, logN = 0;
-  bool persistent[2][5] = {};   // [alg][d/2 index]: cooperative launch fits
+  bool persistent[2][5][2] = {};   // [alg][d/2 index][traced]: cooperative launch fits
   uint64_t bar_ticks = 0;       // bound of one grid-barrier wait (device wall-clock ticks)
   int64_t oB = 0, oS = 0, oT1 = 0, oT2 = 0, oLo = 0, oHi = 0, oK1 = 0, oP = 0, oY = 0, oC = 0, oYh = 0;
   size_t bytes = 0;             // size of the memory block
@@ -232,9 +232,9 @@ struct Plan {
 // returned with the process.
 auto& g_plans = *new std::map<std::tuple<int, int64_t, int>, std::unique_ptr<Plan>>();
 
-int solve_blocks_per_cu_dispatch(int logN, int alg, int d2) {
+int solve_blocks_per_cu_dispatch(int logN, int alg, int d2, bool tr) {
   switch (logN) {
-#define CS_CASE(L) case L: return solve_blocks_per_cu<L>(alg, d2);
+#define CS_CASE(L) case L: return tr ? solve_blocks_per_cu<L, true>(alg, d2) : solve_blocks_per_cu<L, false>(alg, d2);
     CS_CASE(7) CS_CASE(8) CS_CASE(9) CS_CASE(10) CS_CASE(11) CS_CASE(12) CS_CASE(13) CS_CASE(14)
     CS_CASE(15) CS_CASE(16) CS_CASE(17) CS_CASE(18) CS_CASE(19) CS_CASE(20) CS_CASE(21)
 #undef CS_CASE
@@ -242,9 +242,9 @@ int solve_blocks_per_cu_dispatch(int logN, int alg, int d2) {
   }
 }
 
-hipError_t launch_solve_dispatch(int logN, int alg, int d2, const SolveArgs& a, hipStream_t s) {
+hipError_t launch_solve_dispatch(int logN, int alg, int d2, bool tr, const SolveArgs& a, hipStream_t s) {
   switch (logN) {
-#define CS_CASE(L) case L: return launch_solve<L>(alg, d2, a, s);
+#define CS_CASE(L) case L: return tr ? launch_solve<L, true>(alg, d2, a, s) : launch_solve<L, false>(alg, d2, a, s);
     CS_CASE(7) CS_CASE(8) CS_CASE(9) CS_CASE(10) CS_CASE(11) CS_CASE(12) CS_CASE(13) CS_CASE(14)
     CS_CASE(15) CS_CASE(16) CS_CASE(17) CS_CASE(18) CS_CASE(19) CS_CASE(20) CS_CASE(21)
 #undef CS_CASE
@@ -261,7 +261,7 @@ struct DevInfo {
   bool ready = false;
   int cus = 0;
   uint64_t bar_ticks = 0;
-  bool persistent[kMaxLogNPersistent + 1][2][4] = {};   // [log2 N][alg][log2 (d/2)]
+  bool persistent[kMaxLogNPersistent + 1][2][4][2] = {};   // [log2 N][alg][log2 (d/2)][traced]
 };
 DevInfo g_dev[kMaxDevices];
 
@@ -278,10 +278,11 @@ cs_status dev_info(int dev, const DevInfo** out) {
       const int N1 = (L % 2) ? (1 << ((L - 1) / 2)) : (1 << (L / 2 - 1));
       const int N2 = (1 << L) / N1;
       for (int alg = 0; alg < 2; ++alg)
-        for (int k = 0; k < 4; ++k) {
-          const int nb = solve_blocks_per_cu_dispatch(L, alg, 1 << k);
-          di.persistent[L][alg][k] = nb >= 1 && int64_t(nb) * di.cus >= N2 / kColsPerBlock;
-        }
+        for (int k = 0; k < 4; ++k)
+          for (int tr = 0; tr < 2; ++tr) {
+            const int nb = solve_blocks_per_cu_dispatch(L, alg, 1 << k, tr != 0);
+            di.persistent[L][alg][k][tr] = nb >= 1 && int64_t(nb) * di.cus >= N2 / kColsPerBlock;
+          }
     }
     di.ready = true;
   }
@@ -329,8 +330,9 @@ cs_status plan_geometry(int dev, int64_t n, int d, Plan& p) {
   p.bar_ticks = di->bar_ticks;
   for (int alg = 0; alg < 2; ++alg)
     for (int k = 0; k < 4; ++k)
-      p.persistent[alg][k] = p.logN >= kMinLogNPersistent && p.logN <= kMaxLogNPersistent &&
-                             di->persistent[p.logN][alg][k];
+      for (int tr = 0; tr < 2; ++tr)
+        p.persistent[alg][k][tr] = p.logN >= kMinLogNPersistent && p.logN <= kMaxLogNPersistent &&
+                                   di->persistent[p.logN][alg][k][tr];
   return CS_OK;
 }
 
@@ -656,8 +658,8 @@ cs_status setup_yhat(const Plan& P, const float* y, hipStream_t s) {
 }
 
 // Whether this solve runs as one cooperative launch.
-cs_status use_persistent(const Plan& P, int alg, bool* out) {
-  const bool fits = P.persistent[alg][ilog2(P.d / 2)];
+cs_status use_persistent(const Plan& P, int alg, bool traced, bool* out) {
+  const bool fits = P.persistent[alg][ilog2(P.d / 2)][traced ? 1 : 0];
   if (g_path == 2 && !fits)
     return fail(CS_ENOTSUP, "persistent solver not available for n=%lld d=%d", (long long)P.n, P.d);
   *out = (g_path == 2) || (g_path == 0 && fits);
@@ -835,7 +837,7 @@ cs_status ista_run(const Plan& V, const float* c, const float* y, float lambda, 
   if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
   if ((st = setup_yhat(*P, y, s)) != CS_OK) return st;
   bool pers = false;
-  if (!obj && (st = use_persistent(*P, 0, &pers)) != CS_OK) return st;
+  if ((st = use_persistent(*P, 0, obj != nullptr, &pers)) != CS_OK) return st;
   if (pers) {
     // barrier counters start at zero (bit pattern of 0.0f); the error flag is
     // cleared by cs_check_device
@@ -845,7 +847,14 @@ cs_status ista_run(const Plan& V, const float* c, const float* y, float lambda, 
     sa.iters = iters;
     sa.tau = tau;
     sa.thr = tau * lambda;
-    CS_LAUNCH(maybe_timed(timing, T_S_ISTA, s, [&] { return launch_solve_dispatch(P->logN, 0, d / 2, sa, s); }));
+    // objective trace: one residual and one l1 partial per workgroup and
+    // iteration (G = N2 / 8 workgroups), reduced after the launch
+    const int G = P->N2 / kColsPerBlock;
+    if (obj && (st = get_objbuf(*P, iters, &sa.res, &sa.l1, s)) != CS_OK) return st;
+    CS_LAUNCH(maybe_timed(timing, T_S_ISTA, s,
+                          [&] { return launch_solve_dispatch(P->logN, 0, d / 2, obj != nullptr, sa, s); }));
+    if (obj && (st = objective_reduce(sa.res, G, sa.l1, G, 0.5 / double(n / d), double(lambda), obj, iters, s)) != CS_OK)
+      return st;
     return CS_OK;
   }
   if ((st = fill(reinterpret_cast<float*>(P->Y), size_t(P->N) * 2, 0.0f, s)) != CS_OK) return st;
@@ -1416,7 +1425,7 @@ cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, fl
   if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
   if ((st = setup_yhat(*P, y, s)) != CS_OK) return st;
   bool pers = false;
-  if (!obj && (st = use_persistent(*P, 1, &pers)) != CS_OK) return st;
+  if ((st = use_persistent(*P, 1, obj != nullptr, &pers)) != CS_OK) return st;
   if (pers) {
     if ((st = fill(reinterpret_cast<float*>(P->bar), kBarErr, 0.0f, s)) != CS_OK) return st;
     SolveArgs sa = solve_args(*P);
@@ -1427,7 +1436,11 @@ cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, fl
     sa.inv_rho = float(1.0 / double(rho));
     sa.d_rho = float(double(d) * double(rho));
     sa.thr = float(double(lambda) / double(rho));
-    CS_LAUNCH(timed(T_S_ADMM, s, [&] { return launch_solve_dispatch(P->logN, 1, d / 2, sa, s); }));
+    const int G = P->N2 / kColsPerBlock;
+    if (obj && (st = get_objbuf(*P, iters, &sa.res, &sa.l1, s)) != CS_OK) return st;
+    CS_LAUNCH(timed(T_S_ADMM, s, [&] { return launch_solve_dispatch(P->logN, 1, d / 2, obj != nullptr, sa, s); }));
+    if (obj && (st = objective_reduce(sa.res, G, sa.l1, G, 0.5 / double(n / d), double(lambda), obj, iters, s)) != CS_OK)
+      return st;
     g_err.clear();
     return CS_OK;
   }

@@ -87,6 +87,10 @@ struct SolveArgs {
   float thr;               // ISTA: tau*lam; ADMM: lam/rho
   float inv_n, inv_d;
   float rho, inv_rho, d_rho;
+  double* res;             // objective trace (traced instances): per iteration t
+  double* l1;              //   and workgroup g, res[(t-1) G + g] = sum over g's
+                           //   m-point bins of |Y_hat - S|^2 for x(t) and
+                           //   l1[(t-1) G + g] = sum of |x(t)| over g's columns
 };
 
 // 16-byte forms of ld_coh / st_coh (two adjacent float2) for the register-
@@ -118,12 +122,17 @@ __device__ __forceinline__ void st_coh_pair(__amdgpu_buffer_rsrc_t rs, unsigned 
 // (N2-p_l) mod N2 in row 0) at indices 7-RHO-l*(8/D2) of Bv (MK = 0) or
 // (8-RHO-l*(8/D2)) mod 8 (MK = 1).  A and Bv may be the same array: every
 // input is read before any output is written.  WB = false for the classes
-// that are their own mirror (row 0, k2 = 0 and M/2).
-template <int D2, int M, int RHO, int MK, bool WB, int ALG, typename Args>
+// that are their own mirror (row 0, k2 = 0 and M/2).  ALG 2 only adds the
+// class's squared residual to racc (the final iterate's trace entry); with
+// TR, ALG 0 and 1 add it too (ISTA: of the input iterate; ADMM: of the
+// updated x).  A class and its mirror bin count twice, a self-mirror class
+// once (Parseval over the m-point spectrum).
+template <int D2, int M, int RHO, int MK, bool WB, int ALG, bool TR, typename Args>
 __device__ __forceinline__ void class_step(float2 (&A)[8], float2 (&Bv)[8], const float2 (&gca)[D2],
                                            const float2 (&gcb)[D2], float2 gy, unsigned k2, float2 wk1,
-                                           const float2* __restrict__ tp, const Args& a) {
+                                           const float2* __restrict__ tp, const Args& a, float& racc) {
   constexpr int RM = 8 / D2;
+  constexpr float RW = WB ? 2.0f : 1.0f;
   float2 Xa[D2], Xb[D2], gw[D2];
 #pragma unroll
   for (int l = 0; l < D2; ++l) {
@@ -139,11 +148,18 @@ __device__ __forceinline__ void class_step(float2 (&A)[8], float2 (&Bv)[8], cons
     Xb[l] = cconj(csub(P, wq));
   }
   float2 Va[D2], Vb[D2];
-  if constexpr (ALG == 0) {
+  if constexpr (ALG == 2) {
+    float2 s1 = c2(0.f, 0.f), s2 = c2(0.f, 0.f);
+#pragma unroll
+    for (int l = 0; l < D2; ++l) { s1 = cadd(s1, cmul(gca[l], Xa[l])); s2 = cadd(s2, cmul(gcb[l], Xb[l])); }
+    racc += RW * cabs2(csub(gy, cscale(cadd(s1, cconj(s2)), a.inv_d)));
+    return;
+  } else if constexpr (ALG == 0) {
     float2 s1 = c2(0.f, 0.f), s2 = c2(0.f, 0.f);
 #pragma unroll
     for (int l = 0; l < D2; ++l) { s1 = cadd(s1, cmul(gca[l], Xa[l])); s2 = cadd(s2, cmul(gcb[l], Xb[l])); }
     const float2 S = cscale(cadd(s1, cconj(s2)), a.inv_d);
+    if constexpr (TR) racc += RW * cabs2(csub(gy, S));
     const float2 E = cscale(csub(gy, S), a.tau);
     const float2 Ec = cconj(E);
 #pragma unroll
@@ -167,6 +183,12 @@ __device__ __forceinline__ void class_step(float2 (&A)[8], float2 (&Bv)[8], cons
     for (int l = 0; l < D2; ++l) {
       Va[l] = cadd(Xa[l], cconjmul(gca[l], E));
       Vb[l] = cadd(Xb[l], cconjmul(gcb[l], Ec));
+    }
+    if constexpr (TR) {
+      float2 s1 = c2(0.f, 0.f), s2 = c2(0.f, 0.f);
+#pragma unroll
+      for (int l = 0; l < D2; ++l) { s1 = cadd(s1, cmul(gca[l], Va[l])); s2 = cadd(s2, cmul(gcb[l], Vb[l])); }
+      racc += RW * cabs2(csub(gy, cscale(cadd(s1, cconj(s2)), a.inv_d)));
     }
   }
 #pragma unroll
@@ -232,7 +254,11 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned target, int
   __syncthreads();
 }
 
-template <int N1, int N2, int D2, int AI, int ALG>  // ALG 0: ISTA, 1: ADMM
+// ALG 0: ISTA, 1: ADMM.  TR: also write the objective trace's per-workgroup
+// partial sums (a.res, a.l1); ISTA then takes one more forward column
+// transform and a residual-only row pass after the last iteration, for the
+// final iterate's residual.
+template <int N1, int N2, int D2, int AI, int ALG, bool TR = false>
 __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
   constexpr int T = kPThreads;
   constexpr int CB = kColsPerBlock;
@@ -364,20 +390,21 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
       });
     }
     // class step for slot KS with mapping (RHO, MK, WB) on arrays (X, Y)
-    auto cstep = [&](auto KS, auto RH, auto MKc, auto WBc, float2 (&X)[8], float2 (&Yv)[8]) __attribute__((always_inline)) {
+    auto cstep = [&](auto AL, auto KS, auto RH, auto MKc, auto WBc, float2 (&X)[8], float2 (&Yv)[8],
+                     float& racc) __attribute__((always_inline)) {
       constexpr int ks = decltype(KS)::value;
       if constexpr (CS_REG_HOIST) {
         bool valid;
         int mode;
         const unsigned k2 = slot_k2(ks, valid, mode);   // recomputed: cheaper than a held register
-        class_step<D2, M, decltype(RH)::value, decltype(MKc)::value, decltype(WBc)::value, ALG>(
-            X, Yv, rca[ks], rcb[ks], ryv[ks], k2, wk1, tp, a);
+        class_step<D2, M, decltype(RH)::value, decltype(MKc)::value, decltype(WBc)::value, decltype(AL)::value, TR>(
+            X, Yv, rca[ks], rcb[ks], ryv[ks], k2, wk1, tp, a, racc);
       } else {
         float2 gca[D2], gcb[D2], gy;
         unsigned k2;
         load_ops(ks, gca, gcb, gy, k2);
-        class_step<D2, M, decltype(RH)::value, decltype(MKc)::value, decltype(WBc)::value, ALG>(
-            X, Yv, gca, gcb, gy, k2, wk1, tp, a);
+        class_step<D2, M, decltype(RH)::value, decltype(MKc)::value, decltype(WBc)::value, decltype(AL)::value, TR>(
+            X, Yv, gca, gcb, gy, k2, wk1, tp, a, racc);
       }
     };
     auto row_elem = [&](unsigned r) __attribute__((always_inline)) -> unsigned { return (wp * N2 + rt + r * Q) * 2; };
@@ -522,35 +549,37 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
         reg_stage_last<N2, RA, false, false, LDA>(lds, t2, vb, sB, jB);
       }
       __syncthreads();
+      float racc = 0.0f;
       {
+        using AL_ = std::integral_constant<int, ALG>;
         using std::integral_constant;
         using I0 = integral_constant<int, 0>;
         using I1 = integral_constant<int, 1>;
         using BT = std::true_type;
         using BF = std::false_type;
         if (cat == 0) {
-          static_for<0, RM>([&](auto K) __attribute__((always_inline)) { cstep(K, K, I0{}, BT{}, va, vb); });
+          static_for<0, RM>([&](auto K) __attribute__((always_inline)) { cstep(AL_{}, K, K, I0{}, BT{}, va, vb, racc); });
         } else if (cat == 1 || cat == 3) {
           if constexpr (RM >= 2) {
             static_for<0, RM / 2>([&](auto K) __attribute__((always_inline)) {
-              cstep(K, K, I0{}, BT{}, va, vb);
-              cstep(integral_constant<int, RM / 2 + decltype(K)::value>{}, K, I0{}, BT{}, vb, va);
+              cstep(AL_{}, K, K, I0{}, BT{}, va, vb, racc);
+              cstep(AL_{}, integral_constant<int, RM / 2 + decltype(K)::value>{}, K, I0{}, BT{}, vb, va, racc);
             });
           } else {
-            cstep(I0{}, I0{}, I0{}, BT{}, va, vb);
+            cstep(AL_{}, I0{}, I0{}, I0{}, BT{}, va, vb, racc);
           }
         } else if (cat == 2) {
           if constexpr (RM >= 2) {
             static_for<0, RM / 2 + 1>([&](auto K) __attribute__((always_inline)) {
               constexpr int k = decltype(K)::value;
-              cstep(K, K, I1{}, std::bool_constant<(k != 0 && k != RM / 2)>{}, va, va);
+              cstep(AL_{}, K, K, I1{}, std::bool_constant<(k != 0 && k != RM / 2)>{}, va, va, racc);
             });
             static_for<0, RM / 2>([&](auto K) __attribute__((always_inline)) {
-              cstep(integral_constant<int, RM / 2 + 1 + decltype(K)::value>{}, K, I0{}, BT{}, vb, vb);
+              cstep(AL_{}, integral_constant<int, RM / 2 + 1 + decltype(K)::value>{}, K, I0{}, BT{}, vb, vb, racc);
             });
           } else {
-            cstep(I0{}, I0{}, I1{}, BF{}, va, va);
-            cstep(I1{}, I0{}, I0{}, BF{}, vb, vb);
+            cstep(AL_{}, I0{}, I0{}, I1{}, BF{}, va, va, racc);
+            cstep(AL_{}, I1{}, I0{}, I0{}, BF{}, vb, vb, racc);
           }
         }
       }
@@ -565,6 +594,11 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
         reg_stage_last<N2, RA, true, false, LDA>(lds, t2, vb, 2 * rpi + 1, rt);
 #pragma unroll
         for (int r = 0; r < 8; ++r) st_coh_pair(rs, row_elem(r), va[r], vb[r]);
+      }
+      if constexpr (TR) {
+        // ISTA: residual of x(t-1) (none at t = 1); ADMM: of the updated x(t)
+        const double rs_ = block_sum<T>(double(racc), tid);
+        if (tid == 0 && (ALG == 1 || t >= 2)) a.res[size_t(ALG == 1 ? t - 1 : t - 2) * G + g] = rs_;
       }
       grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err, a.max_ticks);
 
@@ -584,15 +618,18 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
       __syncthreads();
       const bool last = (t == a.iters);
       const float thr = a.thr;
+      float l1acc = 0.0f;
       if (cact) {
         auto epi = [&](float2& v, float2& s, unsigned j, unsigned r) __attribute__((always_inline)) {
           if constexpr (ALG == 0) {
             const float2 w = cadd(s, v);
             const float2 xv = c2(soft(w.x, thr), soft(w.y, thr));
+            if constexpr (TR) l1acc += fabsf(xv.x) + fabsf(xv.y);
             s = xv;
             v = xv;
           } else {
             const float2 xv = v;
+            if constexpr (TR) l1acc += fabsf(xv.x) + fabsf(xv.y);
             const float2 xu = cadd(xv, s);
             const float2 zv = c2(soft(xu.x, thr), soft(xu.y, thr));
             const float2 u1 = csub(xu, zv);
@@ -611,9 +648,72 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
           epi(B[r], stB[r], cjB, r);
         }
       }
-      if (!last) {
+      if constexpr (TR) {
+        const double l1_ = block_sum<T>(double(l1acc), tid);
+        if (tid == 0) a.l1[size_t(t - 1) * G + g] = l1_;
+      }
+      // a traced ISTA also transforms x(T), for its residual below
+      if (!last || (TR && ALG == 0)) {
         col_forward(A, B);
         grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err, a.max_ticks);
+      }
+    }
+
+    if constexpr (TR && ALG == 0) {
+      // residual of x(T): forward row transforms and the class residuals
+      if (a.iters > 0) {
+        asm volatile("" : "+v"(rpi), "+v"(rt), "+v"(wp), "+v"(jA), "+v"(jB), "+v"(sA), "+v"(sB));
+        float2 va[8], vb[8];
+        if (ract) {
+#pragma unroll
+          for (int r = 0; r < 8; ++r) ld_coh_pair(rs, row_elem(r), va[r], vb[r]);
+          reg_stage_first<N2, RA, false, false, LDA>(lds, va, 2 * rpi, rt);
+          reg_stage_first<N2, RA, false, false, LDA>(lds, vb, 2 * rpi + 1, rt);
+        }
+        __syncthreads();
+        lds_fft_mid<N2, RA, T, false, false, LDA>(lds, t2, tid);
+        if (ract) {
+          reg_stage_last<N2, RA, false, false, LDA>(lds, t2, va, sA, jA);
+          reg_stage_last<N2, RA, false, false, LDA>(lds, t2, vb, sB, jB);
+        }
+        __syncthreads();
+        // the class dispatch of the iteration in residual-only mode
+        float racc = 0.0f;
+        {
+          using AL_ = std::integral_constant<int, 2>;
+          using std::integral_constant;
+          using I0 = integral_constant<int, 0>;
+          using I1 = integral_constant<int, 1>;
+          using BT = std::true_type;
+          using BF = std::false_type;
+          if (cat == 0) {
+            static_for<0, RM>([&](auto K) __attribute__((always_inline)) { cstep(AL_{}, K, K, I0{}, BT{}, va, vb, racc); });
+          } else if (cat == 1 || cat == 3) {
+            if constexpr (RM >= 2) {
+              static_for<0, RM / 2>([&](auto K) __attribute__((always_inline)) {
+                cstep(AL_{}, K, K, I0{}, BT{}, va, vb, racc);
+                cstep(AL_{}, integral_constant<int, RM / 2 + decltype(K)::value>{}, K, I0{}, BT{}, vb, va, racc);
+              });
+            } else {
+              cstep(AL_{}, I0{}, I0{}, I0{}, BT{}, va, vb, racc);
+            }
+          } else if (cat == 2) {
+            if constexpr (RM >= 2) {
+              static_for<0, RM / 2 + 1>([&](auto K) __attribute__((always_inline)) {
+                constexpr int k = decltype(K)::value;
+                cstep(AL_{}, K, K, I1{}, std::bool_constant<(k != 0 && k != RM / 2)>{}, va, va, racc);
+              });
+              static_for<0, RM / 2>([&](auto K) __attribute__((always_inline)) {
+                cstep(AL_{}, integral_constant<int, RM / 2 + 1 + decltype(K)::value>{}, K, I0{}, BT{}, vb, vb, racc);
+              });
+            } else {
+              cstep(AL_{}, I0{}, I0{}, I1{}, BF{}, va, va, racc);
+              cstep(AL_{}, I1{}, I0{}, I0{}, BF{}, vb, vb, racc);
+            }
+          }
+        }
+        const double rs_ = block_sum<T>(double(racc), tid);
+        if (tid == 0) a.res[size_t(a.iters - 1) * G + g] = rs_;
       }
     }
 
@@ -728,15 +828,12 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
       }
     }
   }
-  for (int t = 1; t <= a.iters; ++t) {
-    // keep per-thread index arithmetic inside the iteration: hoisting it out
-    // of the loop keeps dozens of addresses live and forces spills
-    asm volatile("" : "+v"(tid));
-    // ---- row pass: forward rows, alias-class update, inverse rows ----------
-    // Issue every row load before the first LDS store.
+  // row pass, first half: the workgroup's row pairs from Y (zeros when
+  // zero_in) into LDS, forward row transforms.  Every row load is issued
+  // before the first LDS store.
+  auto row_forward = [&](bool zero_in) {
     {
       float2 rv[EA];
-      const bool zero_in = (t == 1) && !(ALG == 1 && a.warm);
 #pragma unroll
       for (int k = 0; k < EA; ++k) {
         const unsigned i = tid + k * T;
@@ -755,6 +852,14 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
     }
     __syncthreads();
     lds_fft<N2, RA, T, false, false, LDA>(lds, t2, tid);
+  };
+  for (int t = 1; t <= a.iters; ++t) {
+    // keep per-thread index arithmetic inside the iteration: hoisting it out
+    // of the loop keeps dozens of addresses live and forces spills
+    asm volatile("" : "+v"(tid));
+    // ---- row pass: forward rows, alias-class update, inverse rows ----------
+    row_forward((t == 1) && !(ALG == 1 && a.warm));
+    float racc = 0.0f;
 #pragma unroll
     for (int k = 0; k < GPT; ++k) {
       const unsigned q = tid + k * T;
@@ -783,6 +888,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
 #pragma unroll
         for (int l = 0; l < D2; ++l) { s1 = cadd(s1, cmul(gca[k][l], Xa[l])); s2 = cadd(s2, cmul(gcb[k][l], Xb[l])); }
         const float2 S = cscale(cadd(s1, cconj(s2)), a.inv_d);
+        if constexpr (TR) racc += (write_b ? 2.0f : 1.0f) * cabs2(csub(gy[k], S));
         const float2 E = cscale(csub(gy[k], S), a.tau);
         const float2 Ec = cconj(E);
 #pragma unroll
@@ -808,6 +914,12 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
           Va[l] = cadd(Xa[l], cconjmul(gca[k][l], E));
           Vb[l] = cadd(Xb[l], cconjmul(gcb[k][l], Ec));
         }
+        if constexpr (TR) {
+          float2 s1 = c2(0.f, 0.f), s2 = c2(0.f, 0.f);
+#pragma unroll
+          for (int l = 0; l < D2; ++l) { s1 = cadd(s1, cmul(gca[k][l], Va[l])); s2 = cadd(s2, cmul(gcb[k][l], Vb[l])); }
+          racc += (write_b ? 2.0f : 1.0f) * cabs2(csub(gy[k], cscale(cadd(s1, cconj(s2)), a.inv_d)));
+        }
       }
 #pragma unroll
       for (int l = 0; l < D2; ++l) {
@@ -830,6 +942,11 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
         st_coh(&Yg[w * (2 * N2) + i % (2 * N2)],
                lds[lpr((2 * (i / (2 * N2)) + (i & 1)) * LDA + (i % (2 * N2)) / 2)]);
       }
+    }
+    if constexpr (TR) {
+      // ISTA: residual of x(t-1) (none at t = 1); ADMM: of the updated x(t)
+      const double rs_ = block_sum<T>(double(racc), tid);
+      if (tid == 0 && (ALG == 1 || t >= 2)) a.res[size_t(ALG == 1 ? t - 1 : t - 2) * G + g] = rs_;
     }
     grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err, a.max_ticks);
 
@@ -854,6 +971,7 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
     lds_fft<N1, CB, T, true, true, N1>(lds, t1, tid);
     const bool last = (t == a.iters);
     const float thr = a.thr;
+    float l1acc = 0.0f;
 #pragma unroll
     for (int k = 0; k < EB; ++k) {
       const unsigned e = tid + k * T;
@@ -861,10 +979,12 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
         if constexpr (ALG == 0) {
           const float2 v = cadd(st[k], lds[lp(e)]);
           const float2 xv = c2(soft(v.x, thr), soft(v.y, thr));
+          if constexpr (TR) l1acc += fabsf(xv.x) + fabsf(xv.y);
           st[k] = xv;
           lds[lp(e)] = xv;
         } else {
           const float2 xv = lds[lp(e)];
+          if constexpr (TR) l1acc += fabsf(xv.x) + fabsf(xv.y);
           const float2 xu = cadd(xv, st[k]);
           const float2 zv = c2(soft(xu.x, thr), soft(xu.y, thr));
           const float2 u1 = csub(xu, zv);
@@ -879,10 +999,49 @@ __global__ __launch_bounds__(kPThreads) void k_solve(SolveArgs a) {
         }
       }
     }
-    if (!last) {
+    if constexpr (TR) {
+      const double l1_ = block_sum<T>(double(l1acc), tid);
+      if (tid == 0) a.l1[size_t(t - 1) * G + g] = l1_;
+    }
+    // a traced ISTA also transforms x(T), for its residual below
+    if (!last || (TR && ALG == 0)) {
       __syncthreads();
       col_forward_store();
       grid_barrier<NC>(a.bar, (++nbar) * PER_C, a.err, a.max_ticks);
+    }
+  }
+
+  if constexpr (TR && ALG == 0) {
+    // residual of x(T): forward row transforms and the class residuals
+    if (a.iters > 0) {
+      asm volatile("" : "+v"(tid));
+      row_forward(false);
+      float racc = 0.0f;
+#pragma unroll
+      for (int k = 0; k < GPT; ++k) {
+        const unsigned q = tid + k * T;
+        if (q >= (unsigned)ncls) continue;
+        const Cls c = decode(q);
+        const bool write_b = !(c.mode == 1 && (c.k2 == 0 || c.k2 == (M >> 1)));
+        const float2 wk1 = a.twk1[c.rowa];
+        float2 s1 = c2(0.f, 0.f), s2 = c2(0.f, 0.f);
+#pragma unroll
+        for (int l = 0; l < D2; ++l) {
+          const int p = c.k2 + l * M;
+          const int qq = (c.mode == 1) ? ((N2 - p) & (N2 - 1)) : (N2 - 1 - p);
+          const float2 gw = cmul(wk1, tp[p]);
+          const float2 za = lds[lpr(c.sa * LDA + p)];
+          const float2 zbc = cconj(lds[lpr(c.sb * LDA + qq)]);
+          const float2 P = cscale(cadd(za, zbc), 0.5f);
+          const float2 Q = cscale(cmulmi(csub(za, zbc)), 0.5f);
+          const float2 wq = cmul(gw, Q);
+          s1 = cadd(s1, cmul(gca[k][l], cadd(P, wq)));
+          s2 = cadd(s2, cmul(gcb[k][l], cconj(csub(P, wq))));
+        }
+        racc += (write_b ? 2.0f : 1.0f) * cabs2(csub(gy[k], cscale(cadd(s1, cconj(s2)), a.inv_d)));
+      }
+      const double rs_ = block_sum<T>(double(racc), tid);
+      if (tid == 0) a.res[size_t(a.iters - 1) * G + g] = rs_;
     }
   }
 

@@ -105,21 +105,62 @@ def test_trace_other_shapes(n, d, k):
     assert np.max(np.abs(h(oa) - ra) / ra) <= F_TOL
 
 
-def test_trace_does_not_change_the_iterates(parity_signal):
-    """A trace switches to the two-launch schedule and adds reductions only:
-    the iterates equal those of the two-launch schedule without a trace."""
+@pytest.mark.parametrize("path", ["two_pass", "persistent"])
+def test_trace_does_not_change_the_iterates(parity_signal, path):
+    """A trace only adds reductions: on either schedule the iterates equal
+    those of the same schedule without a trace."""
     pr, _ = parity_signal
     c, yg = g(pr.c), g(pr.y)
-    cs.set_solver_path(cs.PATH_TWO_PASS)
+    cs.set_solver_path(cs.PATH_TWO_PASS if path == "two_pass" else cs.PATH_PERSISTENT)
     try:
         x0 = h(cs.ista_solve(c, pr.d, yg, pr.lam, pr.tau, 50))
         a0 = [h(v) for v in cs.admm_solve(c, pr.d, yg, pr.lam, 1.0, 30)]
+        x1 = h(cs.ista_solve(c, pr.d, yg, pr.lam, pr.tau, 50, obj=trace(50)))
+        a1 = [h(v) for v in cs.admm_solve(c, pr.d, yg, pr.lam, 1.0, 30, obj=trace(30))]
     finally:
         cs.set_solver_path(cs.PATH_AUTO)
-    x1 = h(cs.ista_solve(c, pr.d, yg, pr.lam, pr.tau, 50, obj=trace(50)))
-    a1 = [h(v) for v in cs.admm_solve(c, pr.d, yg, pr.lam, 1.0, 30, obj=trace(30))]
     assert np.array_equal(x0, x1)
     assert all(np.array_equal(p, q) for p, q in zip(a0, a1))
+
+
+@pytest.mark.parametrize("n,d", [(256, 2), (4096, 16), (1 << 16, 4), (1 << 19, 8), (1 << 20, 2), (1 << 22, 4),
+                                 (1 << 22, 16)])
+def test_trace_persistent_matches_two_pass(n, d):
+    """The persistent kernel's trace (per-workgroup partial sums inside the
+    single launch; ISTA's last entry from a residual-only row pass after the
+    loop) against the two-launch schedule's, entry by entry, ISTA from zero
+    and ADMM from zero and warm; both sizes below and above the
+    register-stage threshold (n = 2^20), every d.  Relative 1e-5: the two
+    schedules order the FP32 transforms differently."""
+    pr = problem.build(workloads.signal(n, d, max(2, n // 100), 700 + d))
+    c, yg = g(pr.c), g(pr.y)
+    T = 12
+    out = {}
+    for path in (cs.PATH_TWO_PASS, cs.PATH_PERSISTENT):
+        cs.set_solver_path(path)
+        try:
+            oi, oa, ow = trace(T), trace(T), trace(T)
+            cs.ista_solve(c, d, yg, pr.lam, pr.tau, T, obj=oi)
+            x, z, u = cs.admm_solve(c, d, yg, pr.lam, 0.5, T, obj=oa)
+            cs.admm_solve(c, d, yg, pr.lam, 0.5, T, warm=True, x=x, z=z, u=u, obj=ow)
+            out[path] = [h(oi), h(oa), h(ow)]
+        finally:
+            cs.set_solver_path(cs.PATH_AUTO)
+    cs.check_device()
+    for name, a, b in zip(("ista", "admm", "admm warm"), out[cs.PATH_PERSISTENT], out[cs.PATH_TWO_PASS]):
+        err = np.max(np.abs(a - b) / np.abs(b))
+        assert err <= F_TOL, (name, n, d, err)
+
+
+def test_trace_one_iteration():
+    """T = 1: the only ISTA entry comes from the residual-only pass."""
+    pr = problem.build(workloads.signal(1 << 20, 4, 1000, 42))
+    A = pr.op()
+    y = pr.y.astype(np.float64)
+    obj = trace(1)
+    x = cs.ista_solve(g(pr.c), 4, g(pr.y), pr.lam, pr.tau, 1, obj=obj)
+    ref = fftref.objective(A, y, float(pr.lam), h(x))
+    assert abs(h(obj)[0] - ref) <= F_TOL * ref
 
 
 def test_trace_flags_non_finite_input(parity_signal):
