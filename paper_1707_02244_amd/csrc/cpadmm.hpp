@@ -22,17 +22,26 @@
 //   row pass (frequency side): forward row FFTs of a and b, the real split,
 //     the per-bin update above for bins k and N - k, the inverse split of X
 //     and c_hat X, inverse row FFTs.
-// Ya carries a (in) and x (out), Yb carries b and C x.  During a solve the
-// caller's v array holds P^T y and its z array the indicator of Omega (both
-// rewritten with v and z in the last iteration).
+// Layouts, chosen so that both passes move whole 128-byte runs:
+//   - one spectrum buffer Yab for both signals (a in / x out, b in / C x
+//     out), interleaving each mirror row pair and the two signals:
+//     element (signal g, row k1, column j2) at Yab[((w N2 + j2) 2 + g) 2 + s]
+//     with pair w = min(k1, N1 - k1) and side s = (k1 != w) (pair 0 holds
+//     rows 0 and N1/2).  A row-pass workgroup reads one contiguous block;
+//     a column-pass workgroup of CB columns reads 4 CB contiguous values per
+//     pair.
+//   - the time-domain state of a solve (mu, nu, P^T y and the indicator of
+//     Omega) in column blocks: sample pair i N2 + j2 at [(b N1 + i) CB + c],
+//     b = j2 / CB, c = j2 mod CB, so each column-pass workgroup owns one
+//     contiguous range.  The last column pass writes x, v, z, mu and nu in
+//     natural order into the caller's arrays.
 #pragma once
 #include "kernels.hpp"
 
 namespace cs {
 
 struct CpArgs {
-  float2* Ya;              // [N1][N2] four-step buffer of a / x
-  float2* Yb;              // [N1][N2] four-step buffer of b / C x
+  float2* Yab;             // [N1/2][N2][2][2] four-step buffer of a / x and b / C x
   const float2* chat;      // c_hat table ([k1*N2 + k2], Nyquist at [N])
   const float2* twk1;      // W_n^{k1}
   const float2* twp;       // W_{2 N2}^p
@@ -45,11 +54,15 @@ struct CpArgs {
   float inv_n;
   float rho, sigma, tau, thr;   // thr = alpha / sigma
   float d_in, d_out;            // D on Omega (1 / (1 + rho)) and elsewhere (1 / rho)
-  float* mu;               // state (n)
-  float* nu;               // state (n)
-  float* v;                // P^T y during the solve; v at the end
-  float* z;                // indicator of Omega during the solve; z at the end
-  float* x;                // x at the end
+  float2* mu_b;            // mu, column-blocked (n/2 pairs)
+  float2* nu_b;            // nu, column-blocked
+  const float2* py_b;      // P^T y, column-blocked
+  const float2* om_b;      // indicator of Omega, column-blocked
+  float* mu;               // outputs in natural order, written by the last
+  float* nu;               //   column pass
+  float* v;
+  float* z;
+  float* x;
 };
 
 __device__ __forceinline__ float2 cp_twN(const CpArgs& a, int e) {
@@ -57,32 +70,41 @@ __device__ __forceinline__ float2 cp_twN(const CpArgs& a, int e) {
   return cmul(a.twlo[e & ((1 << a.lo_bits) - 1)], a.twhi[e >> a.lo_bits]);
 }
 
+// Row-pass threads: 512 for rows of 1024 points and more (16 values per
+// thread), else 256.
+constexpr int cp_row_threads(int N2) { return N2 >= 1024 ? 512 : 256; }
+
 // Row pass of row pair w: LDS slots 0, 1 = rows {w, N1 - w} of a, slots 2, 3
-// = the same rows of b ({0, N1/2} for w = 0).
+// = the same rows of b ({0, N1/2} for w = 0); slot g 2 + s is element
+// (j2, g, s) of the pair's contiguous block of Yab.  The FFT twiddles are
+// staged in LDS only where two workgroups still fit on a CU with them
+// (N2 <= 1024); longer rows read them from the global table.
 template <int N2, int T>
-__global__ __launch_bounds__(T) void k_cp_row(CpArgs a) {
+__global__ __launch_bounds__(T, 2) void k_cp_row(CpArgs a) {
   constexpr int LD = N2 + kPadA;
   constexpr int NR = 4 * N2;
   constexpr int EPT = (NR + T - 1) / T;
-  static_assert((lds_rows(4 * LD) + N2) * 8 <= 96 * 1024, "row pass exceeds its LDS budget");
+  constexpr bool TWL = (lds_rows(4 * LD) + N2) * 8 <= 80 * 1024;
+  static_assert(lds_rows(4 * LD) * 8 <= 80 * 1024, "row pass exceeds its LDS budget");
   __shared__ float2 lds[lds_rows(4 * LD)];
-  __shared__ float2 tws[N2];
+  __shared__ float2 tws_l[TWL ? N2 : 1];
+  const float2* tws = TWL ? tws_l : a.tw2;
   const unsigned tid = threadIdx.x;
   const int w = blockIdx.x;
   const int N1 = a.N1;
-  const int ra = w, rb = w ? (N1 - w) : (N1 >> 1);
-  auto src = [&](int slot) -> float2* { return (slot < 2 ? a.Ya : a.Yb) + (size_t)((slot & 1) ? rb : ra) * N2; };
-  for (int i = tid; i < N2; i += T) tws[i] = a.tw2[i];
+  float2* blk = a.Yab + (size_t)w * (4 * N2);
+  if constexpr (TWL)
+    for (int i = tid; i < N2; i += T) tws_l[i] = a.tw2[i];
   float2 rv[EPT];
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const int i = tid + k * T;
-    if (NR % T == 0 || i < NR) rv[k] = src(i / N2)[i % N2];
+    if (NR % T == 0 || i < NR) rv[k] = blk[i];
   }
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const int i = tid + k * T;
-    if (NR % T == 0 || i < NR) lds[lpr((i / N2) * LD + (i % N2))] = rv[k];
+    if (NR % T == 0 || i < NR) lds[lpr((i & 3) * LD + (i >> 2))] = rv[k];
   }
   __syncthreads();
   lds_fft<N2, 4, T, false, false, LD>(lds, tws, tid);
@@ -137,16 +159,19 @@ __global__ __launch_bounds__(T) void k_cp_row(CpArgs a) {
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const int i = tid + k * T;
-    if (NR % T == 0 || i < NR) src(i / N2)[i % N2] = lds[lpr((i / N2) * LD + (i % N2))];
+    if (NR % T == 0 || i < NR) blk[i] = lds[lpr((i & 3) * LD + (i >> 2))];
   }
 }
 
 // Column pass on CB adjacent columns [CB b, CB b + CB): LDS holds the columns
 // of x (sequences 0 .. CB-1) and of C x (CB .. 2CB-1) interleaved, element
-// (sequence s, index i) at [i * 2CB + s].  LAST: write x, v, z and skip the
-// forward transforms.
+// (sequence s, index i) at [i * 2CB + s].  The workgroup's part of Yab is
+// 4 CB contiguous values per row pair: value r of pair w is column
+// j2 = CB b + r / 4 of signal (r / 2) mod 2, row w (r even) or its mirror.
+// LAST: write x, v, z, mu, nu in natural order and skip the forward
+// transforms.
 template <int N1, int CB, int T, bool LAST>
-__global__ __launch_bounds__(T) void k_cp_col(CpArgs a) {
+__global__ __launch_bounds__(T, 2) void k_cp_col(CpArgs a) {
   constexpr int S = 2 * CB;
   constexpr int NE = N1 * S;
   constexpr int EPT = (NE + T - 1) / T;
@@ -157,49 +182,51 @@ __global__ __launch_bounds__(T) void k_cp_col(CpArgs a) {
   const int j2_0 = blockIdx.x * CB;
   const int N2 = a.N2;
   for (int i = tid; i < N1; i += T) tws[i] = a.tw1[i];
-  auto gaddr = [&](int e, int& s, size_t& j, int& j2, int& k1) {
-    k1 = e / S;
-    const int r = e % S;
-    s = r / CB;
-    j2 = j2_0 + (r % CB);
-    j = (size_t)k1 * N2 + j2;
+  // element e of the workgroup's part of Yab: its global offset, its LDS
+  // slot and its four-step twiddle exponent j2 * k1
+  auto gaddr = [&](int e, size_t& gofs, int& li, int& ex) {
+    const int w = e / (4 * CB), r = e % (4 * CB);
+    const int c = r >> 2, g = (r >> 1) & 1;
+    const int k1 = (r & 1) ? (w ? N1 - w : (N1 >> 1)) : w;
+    gofs = ((size_t)w * N2 + j2_0) * 4 + r;
+    li = k1 * S + g * CB + c;
+    ex = (j2_0 + c) * k1;
   };
   // loads in chunks of CH per thread (all of a chunk in flight at once)
   constexpr int CH = EPT < 8 ? EPT : 8;
 #pragma unroll 1
   for (int k0 = 0; k0 < EPT; k0 += CH) {
     float2 v[CH], t[CH];
+    int l[CH];
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
       const int e = tid + (k0 + k) * T;
       if (FULL || e < NE) {
-        int s, j2, k1;
-        size_t j;
-        gaddr(e, s, j, j2, k1);
-        v[k] = (s ? a.Yb : a.Ya)[j];
-        t[k] = cp_twN(a, j2 * k1);
+        size_t go;
+        int ex;
+        gaddr(e, go, l[k], ex);
+        v[k] = a.Yab[go];
+        t[k] = cp_twN(a, ex);
       }
     }
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
       const int e = tid + (k0 + k) * T;
-      if (FULL || e < NE) lds[lp(e)] = cmulc(v[k], t[k]);
+      if (FULL || e < NE) lds[lp(l[k])] = cmulc(v[k], t[k]);
     }
   }
   __syncthreads();
   lds_fft<N1, S, T, true, true, N1>(lds, tws, tid);
-  // time domain: x at [i*S + c], C x at [i*S + CB + c], sample pair j = i*N2 + j2_0 + c
-  float2* mu = reinterpret_cast<float2*>(a.mu);
-  float2* nu = reinterpret_cast<float2*>(a.nu);
-  float2* vv = reinterpret_cast<float2*>(a.v);
-  float2* zz = reinterpret_cast<float2*>(a.z);
+  // time domain: x at [i*S + c], C x at [i*S + CB + c]; sample pair
+  // i*N2 + j2_0 + c, blocked state index blockIdx.x * N1 * CB + q
+  const size_t qb0 = (size_t)blockIdx.x * N1 * CB;
 #pragma unroll 2
   for (int q = tid; q < N1 * CB; q += T) {
     const int i = q / CB, c = q % CB;
-    const size_t j = (size_t)i * N2 + j2_0 + c;
     const float2 x = lds[lp(i * S + c)];
     const float2 cx = lds[lp(i * S + CB + c)];
-    const float2 m0 = mu[j], n0 = nu[j], py = vv[j], om = zz[j];
+    const size_t qb = qb0 + q;
+    const float2 m0 = a.mu_b[qb], n0 = a.nu_b[qb], py = a.py_b[qb], om = a.om_b[qb];
     auto upd = [&](float xe, float cxe, float me, float ne, float pye, float ome, float& ve, float& ze, float& me1,
                    float& ne1) {
       const float dd = ome != 0.0f ? a.d_in : a.d_out;
@@ -211,13 +238,16 @@ __global__ __launch_bounds__(T) void k_cp_col(CpArgs a) {
     float2 v1, z1, m1, n1;
     upd(x.x, cx.x, m0.x, n0.x, py.x, om.x, v1.x, z1.x, m1.x, n1.x);
     upd(x.y, cx.y, m0.y, n0.y, py.y, om.y, v1.y, z1.y, m1.y, n1.y);
-    mu[j] = m1;
-    nu[j] = n1;
     if constexpr (LAST) {
+      const size_t j = (size_t)i * N2 + j2_0 + c;
       reinterpret_cast<float2*>(a.x)[j] = x;
-      vv[j] = v1;
-      zz[j] = z1;
+      reinterpret_cast<float2*>(a.v)[j] = v1;
+      reinterpret_cast<float2*>(a.z)[j] = z1;
+      reinterpret_cast<float2*>(a.mu)[j] = m1;
+      reinterpret_cast<float2*>(a.nu)[j] = n1;
     } else {
+      a.mu_b[qb] = m1;
+      a.nu_b[qb] = n1;
       lds[lp(i * S + c)] = cadd(v1, m1);        // a = v + mu
       lds[lp(i * S + CB + c)] = csub(z1, n1);   // b = z - nu
     }
@@ -228,25 +258,21 @@ __global__ __launch_bounds__(T) void k_cp_col(CpArgs a) {
 #pragma unroll 1
     for (int k0 = 0; k0 < EPT; k0 += CH) {
       float2 t[CH];
+      int l[CH];
+      size_t go[CH];
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const int e = tid + (k0 + k) * T;
         if (FULL || e < NE) {
-          int s, j2, k1;
-          size_t j;
-          gaddr(e, s, j, j2, k1);
-          t[k] = cp_twN(a, j2 * k1);
+          int ex;
+          gaddr(e, go[k], l[k], ex);
+          t[k] = cp_twN(a, ex);
         }
       }
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const int e = tid + (k0 + k) * T;
-        if (FULL || e < NE) {
-          int s, j2, k1;
-          size_t j;
-          gaddr(e, s, j, j2, k1);
-          (s ? a.Yb : a.Ya)[j] = cmul(lds[lp(e)], t[k]);
-        }
+        if (FULL || e < NE) a.Yab[go[k]] = cmul(lds[lp(l[k])], t[k]);
       }
     }
   }
@@ -255,6 +281,8 @@ __global__ __launch_bounds__(T) void k_cp_col(CpArgs a) {
 // Columns per column-pass workgroup: 4 when N1 >= 512 (two signals' columns
 // then fill 64 KiB of LDS), else 8.
 constexpr int cp_cb(int N1) { return N1 >= 512 ? 4 : 8; }
+// Column-pass threads: 512 from N1 = 512 on (16 values per thread), else 256.
+constexpr int cp_col_threads(int N1) { return N1 >= 512 ? 512 : 256; }
 // Largest row / column lengths of these passes (n <= 2^22).
 constexpr int kCpMaxN2 = 2048;
 constexpr int kCpMaxN1 = 1024;

@@ -61,7 +61,7 @@ hipError_t launch_urow<CS_LEN>(int op, int d2, int grid, int batch, const PassAA
 template <>
 hipError_t launch_cp_row<CS_LEN>(int grid, const CpArgs& a, hipStream_t s) {
   if constexpr (CS_LEN <= kCpMaxN2) {
-    k_cp_row<CS_LEN, kThreads><<<dim3(grid), dim3(kThreads), 0, s>>>(a);
+    k_cp_row<CS_LEN, cp_row_threads(CS_LEN)><<<dim3(grid), dim3(cp_row_threads(CS_LEN)), 0, s>>>(a);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;

@@ -49,8 +49,9 @@ template <>
 hipError_t launch_cp_col<CS_LEN>(int last, int grid, const CpArgs& a, hipStream_t s) {
   if constexpr (CS_LEN <= kCpMaxN1) {
     constexpr int CB = cp_cb(CS_LEN);
-    if (last) k_cp_col<CS_LEN, CB, kThreads, true><<<dim3(grid), dim3(kThreads), 0, s>>>(a);
-    else k_cp_col<CS_LEN, CB, kThreads, false><<<dim3(grid), dim3(kThreads), 0, s>>>(a);
+    constexpr int T = cp_col_threads(CS_LEN);
+    if (last) k_cp_col<CS_LEN, CB, T, true><<<dim3(grid), dim3(T), 0, s>>>(a);
+    else k_cp_col<CS_LEN, CB, T, false><<<dim3(grid), dim3(T), 0, s>>>(a);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;

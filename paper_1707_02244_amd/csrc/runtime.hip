@@ -552,15 +552,19 @@ hipError_t launchCpCol(const Plan& P, int last, const CpArgs& a, hipStream_t s) 
   }
 }
 
-// P^T y into v (zero elsewhere) and the indicator of Omega into z, for the
-// circulant ADMM with an arbitrary row set; omega is read from `idx` (int32,
-// validated on the host).  v and z are zeroed first by the caller.
-__global__ void k_cp_scatter(const int* __restrict__ idx, int64_t m, const float* __restrict__ y,
-                             float* __restrict__ v, float* __restrict__ z) {
+// P^T y (zero elsewhere) and the indicator of Omega, for the circulant ADMM
+// with an arbitrary row set, into their column-blocked arrays: sample j is
+// component j mod 2 of pair p = j / 2 = i N2 + j2, stored at pair
+// ((j2 / CB) N1 + i) CB + j2 mod CB.  omega is read from `idx` (int32,
+// validated on the host); both arrays are zeroed first by the caller.
+__global__ void k_cp_scatter(const int* __restrict__ idx, int64_t m, const float* __restrict__ y, int N1, int N2,
+                             int CB, float* __restrict__ py, float* __restrict__ om) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < m; i += int64_t(gridDim.x) * blockDim.x) {
     const int j = idx[i];
-    v[j] = y[i];
-    z[j] = 1.0f;
+    const int p = j >> 1, r = p / N2, j2 = p % N2;
+    const int64_t pb = (int64_t(j2 / CB) * N1 + r) * CB + j2 % CB;
+    py[2 * pb + (j & 1)] = y[i];
+    om[2 * pb + (j & 1)] = 1.0f;
   }
 }
 
@@ -743,6 +747,35 @@ cs_status get_objbuf(const Plan& P, int iters, double** res, double** l1, hipStr
   }
   *res = B.p;
   *l1 = B.p + size_t(iters) * nres;
+  return CS_OK;
+}
+
+// Working memory of the circulant ADMM with an arbitrary row set: the
+// interleaved spectrum buffer of both signals (n complex) and the
+// column-blocked mu, nu, P^T y and Omega indicator (n/2 pairs each).  One
+// grow-only buffer per device.
+struct CpBuf {
+  float2* p = nullptr;
+  size_t cap = 0;   // float2 elements
+};
+CpBuf g_cp[kMaxDevices];
+
+cs_status get_cpbuf(const Plan& P, float2** out, hipStream_t s) {
+  const size_t need = size_t(P.n) + 4 * size_t(P.N);
+  if (P.dev < 0 || P.dev >= kMaxDevices) return fail(CS_ENOTSUP, "device %d beyond the supported range", P.dev);
+  std::lock_guard<std::mutex> lk(g_mu);
+  CpBuf& B = g_cp[P.dev];
+  if (B.cap < need) {
+    CS_HIP(hipStreamSynchronize(s));
+    if (B.p) CS_HIP(hipFree(B.p));
+    B.p = nullptr;
+    B.cap = 0;
+    hipError_t e = hipMalloc(&B.p, need * sizeof(float2));
+    if (e != hipSuccess) return fail(CS_ENOMEM, "hipMalloc of %zu bytes for the circulant ADMM failed",
+                                     need * sizeof(float2));
+    B.cap = need;
+  }
+  *out = B.p;
   return CS_OK;
 }
 
@@ -1357,18 +1390,27 @@ cs_status cs_cpadmm_solve(const float* c, int64_t n, const int64_t* omega_host, 
   // Omega's indices go to the device through the caller's x array (n floats
   // >= m ints), which the solve writes only at its end; the copy is waited
   // for before the host vector goes away.
+  float2* W = nullptr;
+  if ((st = get_cpbuf(V, &W, s)) != CS_OK) return st;
+  // W: Yab (n complex), then mu_b, nu_b, py_b, om_b (N pairs each); all
+  // start at zero (a = v + mu = 0, b = z - nu = 0)
+  if ((st = fill(reinterpret_cast<float*>(W), size_t(n) * 2 + 8 * size_t(V.N), 0.0f, s)) != CS_OK) return st;
+  float2* mu_b = W + n;
+  float2* nu_b = mu_b + V.N;
+  float2* py_b = nu_b + V.N;
+  float2* om_b = py_b + V.N;
   int* didx = reinterpret_cast<int*>(x);
   CS_HIP(hipMemcpyAsync(didx, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  k_cp_scatter<<<dim3(unsigned(std::min<int64_t>((m + 255) / 256, 1024))), dim3(256), 0, s>>>(didx, m, y, v, z);
+  k_cp_scatter<<<dim3(unsigned(std::min<int64_t>((m + 255) / 256, 1024))), dim3(256), 0, s>>>(
+      didx, m, y, V.N1, V.N2, cp_cb(V.N1), reinterpret_cast<float*>(py_b), reinterpret_cast<float*>(om_b));
   CS_HIP(hipGetLastError());
   CS_HIP(hipStreamSynchronize(s));
-  // a = v + mu = 0 and b = z - nu = 0 at the start (x = v = z = mu = nu = 0)
-  float2* Yb = V.yhat;   // the plan's second spectrum buffer
-  if ((st = fill(reinterpret_cast<float*>(V.Y), size_t(V.N) * 2, 0.0f, s)) != CS_OK) return st;
-  if ((st = fill(reinterpret_cast<float*>(Yb), size_t(V.N) * 2, 0.0f, s)) != CS_OK) return st;
   CpArgs a{};
-  a.Ya = V.Y;
-  a.Yb = Yb;
+  a.Yab = W;
+  a.mu_b = mu_b;
+  a.nu_b = nu_b;
+  a.py_b = py_b;
+  a.om_b = om_b;
   a.chat = V.chat;
   a.twk1 = V.twk1;
   a.twp = V.twp;
