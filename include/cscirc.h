@@ -13,7 +13,9 @@
  *   - Every float pointer is a DEVICE pointer on the current HIP device,
  *     float32, densely packed, owned by the caller.  The library never frees
  *     or retains it beyond the work it enqueues.
- *   - n is a power of two with 256 <= n <= 2^25; d is 2, 4, 8 or 16; m = n/d.
+ *   - n is a power of two with 256 <= n <= 2^25; d is 1, 2, 4, 8 or 16;
+ *     m = n/d.  d = 1 (A = C, every row kept) runs the two-launch schedule;
+ *     the direct products and the unrolled solver take d >= 2.
  *   - All work is enqueued on `stream` (a hipStream_t; 0 is the null stream)
  *     and the call returns without synchronising.  Outputs are valid once the
  *     stream has been synchronised.

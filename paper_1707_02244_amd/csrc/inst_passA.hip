@@ -15,6 +15,7 @@ hipError_t launch_passA<CS_LEN>(int op, int d2, int grid, const PassAArgs& a, hi
   const dim3 g(grid), b(kThreads);
 #define CS_GROUP_OP(OPV)                                                              \
   switch (d2) {                                                                       \
+    case 0: k_passA<L, OPV, 0><<<g, b, 0, s>>>(a); break;                             \
     case 1: k_passA<L, OPV, 1><<<g, b, 0, s>>>(a); break;                             \
     case 2: k_passA<L, OPV, 2><<<g, b, 0, s>>>(a); break;                             \
     case 4: k_passA<L, OPV, 4><<<g, b, 0, s>>>(a); break;                             \

@@ -211,17 +211,23 @@ __device__ __forceinline__ float2 tw_N(const PassBArgs& a, int e) {
 // ---------------------------------------------------------------------------
 // Pass A.  Workgroup w owns rows {w, N1 - w}; workgroup 0 owns the two rows
 // that are their own mirror images, {0, N1/2}.  Rows are held in LDS slots 0
-// and 1.
+// and 1.  D2 = d/2 bins per alias-class side; D2 = 0 stands for d = 1
+// (m = n): every bin is its own class, and A_ISTA, A_ADMM and A_RES run on
+// the split pairs (k, N - k) with y_hat read at both bins.
 template <int N2, int OP, int D2, int T, bool COH = false, int AI = 1>
 __device__ __forceinline__ void rowpass(const PassAArgs& a, int w0, float2* __restrict__ lds,
                                         const float2* __restrict__ tws, unsigned tid) {
   constexpr int LD = N2 + kPadA;
   constexpr int NR = 2 * AI * N2;                     // elements of the held rows
   constexpr int EPT = (NR + T - 1) / T;               // row elements per thread
-  constexpr bool GROUP = (OP == A_ISTA || OP == A_ADMM || OP == A_ADJ || OP == A_TILE || OP == A_RES);
+  constexpr bool SINGLE = (D2 == 0);                  // d = 1: single-bin classes
+  static_assert(!SINGLE || OP == A_ISTA || OP == A_ADMM || OP == A_RES || OP == A_MUL || OP == A_MULC ||
+                OP == A_SPEC, "single-bin classes: solver and operator modes only");
+  constexpr bool GROUP = !SINGLE && (OP == A_ISTA || OP == A_ADMM || OP == A_ADJ || OP == A_TILE || OP == A_RES);
   constexpr bool NEED_C = (OP == A_ISTA || OP == A_ADMM || OP == A_ADJ || OP == A_RES);
   constexpr bool HAS_RES = (OP == A_ISTA || OP == A_ADMM || OP == A_RES);
-  constexpr int MC = N2 / D2;                         // alias classes per row (= m / N1)
+  constexpr int DA = SINGLE ? 1 : D2;                 // array extent
+  constexpr int MC = N2 / DA;                         // alias classes per row (= m / N1)
   constexpr int GPT = GROUP ? (AI * MC + 1 + T - 1) / T : 1;
   const int N1 = a.N1;
   const float tau = a.tau_dev ? a.tau_dev[a.t] : a.tau;
@@ -252,7 +258,7 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w0, float2* __re
     }
   }
   // class decode: mode 0 = row pair (w > 0); 1 = row 0; 2 = row N1/2 (w = 0)
-  float2 gca[GPT][D2], gcb[GPT][D2], gw[GPT][D2], gy[GPT];
+  float2 gca[GPT][DA], gcb[GPT][DA], gw[GPT][DA], gy[GPT];
   const int M = MC;
   const int ng = (w0 ? M : (M + 1)) + (AI - 1) * M;   // classes of the held pairs
   if constexpr (GROUP) {
@@ -435,6 +441,42 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w0, float2* __re
         a.table[(size_t)rowa * N2 + p] = Xa;
         if (write_b) a.table[(size_t)rowb * N2 + q] = Xb;
         if (mode == 1 && p == 0) a.table[a.N] = Xb;
+      } else if constexpr (SINGLE && OP != A_MUL && OP != A_MULC) {
+        // d = 1: bins k (a) and N - k (b) are separate m-point bins, each
+        // with its own y_hat.  Parseval weights over the n bins: bins 0 and
+        // N once, a self-paired bin (N/2) twice on its own, every other bin
+        // twice (itself and its conjugate).
+        const bool edge = (mode == 1 && p == 0);
+        const float2 ca = a.chat[(size_t)rowa * N2 + p];
+        const float2 cb = edge ? a.chat[a.N] : a.chat[(size_t)rowb * N2 + q];
+        const float2 ya = a.yhat[(size_t)rowa * N2 + p];
+        const float2 yb = edge ? a.yhat[a.N] : a.yhat[(size_t)rowb * N2 + q];
+        const float wa = edge ? 1.0f : 2.0f;
+        const float wb = edge ? 1.0f : (write_b ? 2.0f : 0.0f);
+        float2 Va, Vb;
+        if constexpr (OP == A_RES) {
+          res_acc += wa * cabs2(csub(ya, cmul(ca, Xa))) + wb * cabs2(csub(yb, cmul(cb, Xb)));
+          continue;
+        } else if constexpr (OP == A_ISTA) {
+          // gradient step tau conj(c) (y_hat - c X); the column pass adds x
+          const float2 ra = csub(ya, cmul(ca, Xa)), rb = csub(yb, cmul(cb, Xb));
+          res_acc += wa * cabs2(ra) + wb * cabs2(rb);
+          Va = cconjmul(ca, cscale(ra, tau));
+          Vb = cconjmul(cb, cscale(rb, tau));
+        } else {
+          // Woodbury x-update in residual form with a single bin per class:
+          // X' = W + conj(c) (y_hat - c W) / (rho + |c|^2)
+          const float2 Ea = cscale(csub(ya, cmul(ca, Xa)), 1.0f / (a.rho + cabs2(ca)));
+          const float2 Eb = cscale(csub(yb, cmul(cb, Xb)), 1.0f / (a.rho + cabs2(cb)));
+          Va = cadd(Xa, cconjmul(ca, Ea));
+          Vb = cadd(Xb, cconjmul(cb, Eb));
+          if (a.res) res_acc += wa * cabs2(csub(ya, cmul(ca, Va))) + wb * cabs2(csub(yb, cmul(cb, Vb)));
+        }
+        const float2 vbc = cconj(Vb);
+        const float2 E_ = cscale(cadd(Va, vbc), a.inv_n);
+        const float2 O_ = cscale(cmulc(csub(Va, vbc), wt), a.inv_n);
+        lds[lpr(sa * LD + p)] = cadd(E_, cmuli(O_));
+        if (write_b) lds[lpr(sb * LD + q)] = cconj(csub(E_, cmuli(O_)));
       } else {
         const float2 ca = a.chat[(size_t)rowa * N2 + p];
         const float2 cb = (mode == 1 && p == 0) ? a.chat[a.N] : a.chat[(size_t)rowb * N2 + q];
@@ -660,12 +702,13 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
         reinterpret_cast<float2*>(a.out0)[j] = lds[lp(i)];
       }
       fwd = false;
-    } else {  // B_OUT_DEC: real sample 2j is kept when 2j % d == 0 (d even)
+    } else {  // B_OUT_DEC: real sample 2j is kept when 2j % d == 0 (d even; d = 1 keeps all)
       const int h = a.d >> 1;
       for (int i = tid; i < NE; i += T) {
         const int j1 = i / CB, c = i % CB;
         const size_t j = (size_t)j1 * N2 + j2_0 + c;
-        if ((j % h) == 0) a.out0[j / h] = lds[lp(i)].x;
+        if (h == 0) reinterpret_cast<float2*>(a.out0)[j] = lds[lp(i)];
+        else if ((j % h) == 0) a.out0[j / h] = lds[lp(i)].x;
       }
       fwd = false;
     }
@@ -697,8 +740,10 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
           if constexpr (MODE == B_FWD_REAL) {
             v[k] = reinterpret_cast<const float2*>(a.in0)[j];
           } else if constexpr (MODE == B_FWD_UP) {
+            // P^T r: r_i at real sample d i; pair j holds samples 2j, 2j + 1
             const int h = a.d >> 1;
-            v[k] = c2((j % h) == 0 ? a.in0[j / h] : 0.0f, 0.0f);
+            if (h == 0) v[k] = reinterpret_cast<const float2*>(a.in0)[j];
+            else v[k] = c2((j % h) == 0 ? a.in0[j / h] : 0.0f, 0.0f);
           } else {
             v[k] = csub(reinterpret_cast<const float2*>(a.in0)[j], reinterpret_cast<const float2*>(a.in1)[j]);
           }

@@ -663,7 +663,8 @@ cs_status setup_yhat(const Plan& P, const float* y, hipStream_t s) {
 
 // Whether this solve runs as one cooperative launch.
 cs_status use_persistent(const Plan& P, int alg, bool traced, bool* out) {
-  const bool fits = P.persistent[alg][ilog2(P.d / 2)][traced ? 1 : 0];
+  // d = 1 (single-bin classes) runs the two-launch schedule only
+  const bool fits = P.d >= 2 && P.persistent[alg][ilog2(P.d / 2)][traced ? 1 : 0];
   if (g_path == 2 && !fits)
     return fail(CS_ENOTSUP, "persistent solver not available for n=%lld d=%d", (long long)P.n, P.d);
   *out = (g_path == 2) || (g_path == 0 && fits);
@@ -687,8 +688,8 @@ cs_status check_common(const void* c, int64_t n, int d) {
   if (!is_pow2(n) || n < kMinN || n > kMaxN)
     return fail(CS_EINVAL, "n=%lld must be a power of two in [%lld, %lld]", (long long)n,
                 (long long)kMinN, (long long)kMaxN);
-  if (d != 2 && d != 4 && d != 8 && d != 16)
-    return fail(CS_EINVAL, "d=%d must be 2, 4, 8 or 16", d);
+  if (d != 1 && d != 2 && d != 4 && d != 8 && d != 16)
+    return fail(CS_EINVAL, "d=%d must be 1, 2, 4, 8 or 16", d);
   return CS_OK;
 }
 
@@ -833,6 +834,7 @@ cs_status check_unrolled(const float* c, int64_t n, int d, int Bt, const float* 
                          const float* tau, int K, int every) {
   cs_status st = check_common(c, n, d);
   if (st != CS_OK) return st;
+  if (d < 2) return fail(CS_EINVAL, "d=%d: the unrolled solver needs d >= 2", d);
   if (!y || !lam || !tau) return fail(CS_EINVAL, "y, lam or tau is NULL");
   if (Bt < 1 || Bt > 65535) return fail(CS_EINVAL, "batch=%d must be in [1, 65535]", Bt);
   if (K < 1) return fail(CS_EINVAL, "K=%d must be >= 1", K);
@@ -1095,7 +1097,7 @@ cs_status cs_unrolled_ista_bwd(const float* c, int64_t n, int32_t d, int32_t Bt,
 
 size_t cs_workspace_bytes(int64_t n, int32_t d, int32_t mode) {
   if (mode < 0 || mode > 2) return 0;
-  if (!is_pow2(n) || n < kMinN || n > kMaxN || (d != 2 && d != 4 && d != 8 && d != 16)) return 0;
+  if (!is_pow2(n) || n < kMinN || n > kMaxN || (d != 1 && d != 2 && d != 4 && d != 8 && d != 16)) return 0;
   Plan p;
   plan_layout(n, d, p);
   return p.bytes;
@@ -1248,6 +1250,7 @@ cs_status cs_circ_apply_direct(const float* c, int64_t n, int32_t d, const float
                                cs_stream stream) {
   cs_status st = check_common(c, n, d);
   if (st != CS_OK) return st;
+  if (d < 2) return fail(CS_EINVAL, "d=%d: the direct products take d in {2, 4, 8, 16}", d);
   if (!x || !y) return fail(CS_EINVAL, "x or y is NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   CS_LAUNCH(timed(T_DIRECT, s, [&] { return launch_direct(0, d, c, x, y, n, s); }));
@@ -1259,6 +1262,7 @@ cs_status cs_circ_apply_T_direct(const float* c, int64_t n, int32_t d, const flo
                                  cs_stream stream) {
   cs_status st = check_common(c, n, d);
   if (st != CS_OK) return st;
+  if (d < 2) return fail(CS_EINVAL, "d=%d: the direct products take d in {2, 4, 8, 16}", d);
   if (!r || !x) return fail(CS_EINVAL, "r or x is NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   CS_LAUNCH(timed(T_DIRECT_T, s, [&] { return launch_direct(1, d, c, r, x, n, s); }));

@@ -39,7 +39,7 @@ NULL = ctypes.c_void_p(0)
 FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every case below fails validation first
 
 
-@pytest.mark.parametrize("n,d", [(0, 4), (100, 4), (128, 4), (1 << 26, 4), (4096, 1), (4096, 3),
+@pytest.mark.parametrize("n,d", [(0, 4), (100, 4), (128, 4), (1 << 26, 4), (4096, 3), (4096, 6),
                                  (4096, 32), (4096, 0), (4096, -4)])
 def test_bad_sizes_rejected(n, d):
     lib = cs.load()
@@ -48,6 +48,14 @@ def test_bad_sizes_rejected(n, d):
     assert lib.cs_last_error()
     st = lib.cs_ista_solve(FAKE, n, d, FAKE, 0.1, 0.1, 5, FAKE, NULL, NULL)
     assert st == _lib.CS_EINVAL
+
+
+def test_unrolled_rejects_square_operator():
+    """d = 1 is a valid operator and solver size, but the unrolled solver
+    takes d >= 2: rejected before anything is enqueued."""
+    lib = cs.load()
+    assert lib.cs_unrolled_ista_fwd(FAKE, 4096, 1, 2, FAKE, FAKE, FAKE, 5, 0, FAKE, NULL, NULL) == _lib.CS_EINVAL
+    assert b"d >= 2" in lib.cs_last_error()
 
 
 def test_null_pointers_rejected():

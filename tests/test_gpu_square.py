@@ -1,0 +1,125 @@
+"""GPU parity for d = 1 (A = C: every row kept, m = n), where every alias
+class is a single bin.  Operators, ISTA and ADMM iterates against the dense
+FP64 oracle (Alg. 1 and Alg. 2 with A = C written out) and at a larger size
+against the FFT oracle; the objective trace against the oracle's objective.
+Tolerances as in the other parity tests: relative l2 1e-4 per iterate,
+1e-5 per trace entry, operators to the FP32 transform error."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import dense, fftref, problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1707_02244_amd as cs  # noqa: E402
+
+DEV = torch.device("cuda:0")
+IT_TOL = 1e-4
+F_TOL = 1e-5
+
+
+def g(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def h(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def square():
+    pr = problem.build(workloads.signal(4096, 1, 40, 4242))
+    return pr, pr.A()
+
+
+@pytest.mark.parametrize("n", [256, 4096, 1 << 16, 1 << 21])
+def test_square_operators(n):
+    rng = np.random.default_rng(n)
+    c = rng.standard_normal(n).astype(np.float32)
+    x = rng.standard_normal(n).astype(np.float32)
+    op = fftref.Operator(c.astype(np.float64), 1)
+    y = h(cs.circ_apply(g(c), 1, g(x)))
+    xt = h(cs.circ_apply_T(g(c), 1, g(x)))
+    assert rel(y, op.A(x.astype(np.float64))) <= 1e-5
+    assert rel(xt, op.AT(x.astype(np.float64))) <= 1e-5
+
+
+def test_square_dense_operator_matches(square):
+    pr, A = square
+    x = pr.x_true.astype(np.float64)
+    assert A.shape == (4096, 4096)
+    assert rel(h(cs.circ_apply(g(pr.c), 1, g(pr.x_true))), A @ x) <= 1e-5
+
+
+def test_square_ista_iterates(square):
+    pr, A = square
+    y = pr.y.astype(np.float64)
+    T = 100
+    _, hist = dense.ista(A, y, float(pr.lam), float(pr.tau), T, record=True)
+    for t in (1, 2, 5, 25, 100):
+        got = h(cs.ista_solve(g(pr.c), 1, g(pr.y), pr.lam, pr.tau, t))
+        assert rel(got, hist[t - 1]) <= IT_TOL, t
+
+
+def test_square_admm_iterates(square):
+    pr, A = square
+    y = pr.y.astype(np.float64)
+    rho, T = 1.0, 100
+    _, hist = dense.admm(A, y, float(pr.lam), rho, T, record=True)
+    for t in (1, 2, 5, 25, 100):
+        got = [h(v) for v in cs.admm_solve(g(pr.c), 1, g(pr.y), pr.lam, rho, t)]
+        for name, a_, b_ in zip("xzu", got, hist[t - 1]):
+            assert rel(a_, b_) <= IT_TOL, (t, name)
+
+
+def test_square_traces(square):
+    pr, A = square
+    y = pr.y.astype(np.float64)
+    lam, tau, T = float(pr.lam), float(pr.tau), 60
+    _, hi = dense.ista(A, y, lam, tau, T, record=True)
+    _, ha = dense.admm(A, y, lam, 0.5, T, record=True)
+    oi, oa = torch.empty(T, device=DEV), torch.empty(T, device=DEV)
+    cs.ista_solve(g(pr.c), 1, g(pr.y), pr.lam, pr.tau, T, obj=oi)
+    cs.admm_solve(g(pr.c), 1, g(pr.y), pr.lam, 0.5, T, obj=oa)
+    ri = np.array([dense.objective(A, y, lam, x) for x in hi])
+    ra = np.array([dense.objective(A, y, lam, r[0]) for r in ha])
+    assert np.max(np.abs(h(oi) - ri) / ri) <= F_TOL
+    assert np.max(np.abs(h(oa) - ra) / ra) <= F_TOL
+
+
+def test_square_large_first_iterates():
+    """n = 2^20, d = 1: the first iterates against the FFT oracle."""
+    pr = problem.build(workloads.signal(1 << 20, 1, 2000, 77))
+    op = pr.op()
+    y = pr.y.astype(np.float64)
+    _, hist = fftref.ista(op, y, float(pr.lam), float(pr.tau), 5, record=True)
+    for t in (1, 2, 5):
+        got = h(cs.ista_solve(g(pr.c), 1, g(pr.y), pr.lam, pr.tau, t))
+        assert rel(got, hist[t - 1][1]) <= IT_TOL, t
+    _, ha = fftref.admm(op, y, float(pr.lam), 1.0, 5, record=True)
+    got = [h(v) for v in cs.admm_solve(g(pr.c), 1, g(pr.y), pr.lam, 1.0, 5)]
+    for name, a_, b_ in zip("xzu", got, ha[-1][1:]):
+        assert rel(a_, b_) <= IT_TOL, name
+
+
+def test_square_persistent_path_unsupported(square):
+    """d = 1 runs on the two-launch schedule; asking for the persistent one
+    is refused rather than silently rerouted."""
+    pr, _ = square
+    cs.set_solver_path(cs.PATH_PERSISTENT)
+    try:
+        with pytest.raises(cs.CsError):
+            cs.ista_solve(g(pr.c), 1, g(pr.y), pr.lam, pr.tau, 5)
+    finally:
+        cs.set_solver_path(cs.PATH_AUTO)
+    cs.check_device()
