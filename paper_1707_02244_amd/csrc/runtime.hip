@@ -183,7 +183,8 @@ hipError_t timed_mark(int kind, hipStream_t s, long* tok) {
 namespace {
 using namespace rt;
 
-constexpr int64_t kMinN = 256;
+constexpr int64_t kMinN = 64;
+constexpr int64_t kCpMinN = 256;   // circulant ADMM with an arbitrary row set
 constexpr int64_t kMaxN = int64_t(1) << 25;
 constexpr int64_t kCpMaxN = int64_t(1) << 22;   // circulant ADMM with an arbitrary row set
 constexpr int kMinLogNPersistent = 7;    // N = n/2 = 2^7 .. 2^21: one cooperative launch per solve
@@ -508,6 +509,7 @@ hipError_t launchA(const Plan& P, int op, const PassAArgs& a, hipStream_t s) {
   const int grid = P.N1 / 2;
   const int d2 = P.d / 2;
   switch (P.N2) {
+    case 8: return launch_passA<8>(op, d2, grid, a, s);
     case 16: return launch_passA<16>(op, d2, grid, a, s);
     case 32: return launch_passA<32>(op, d2, grid, a, s);
     case 64: return launch_passA<64>(op, d2, grid, a, s);
@@ -585,6 +587,7 @@ __global__ void k_box_blur(const float* __restrict__ c, int64_t n, int L, float*
 hipError_t launchB(const Plan& P, int mode, const PassBArgs& a, hipStream_t s) {
   const int grid = P.N2 / kColsPerBlock;
   switch (P.N1) {
+    case 4: return launch_passB<4>(mode, grid, a, s);
     case 8: return launch_passB<8>(mode, grid, a, s);
     case 16: return launch_passB<16>(mode, grid, a, s);
     case 32: return launch_passB<32>(mode, grid, a, s);
@@ -603,7 +606,7 @@ hipError_t launchUA(const Plan& P, int op, int batch, const PassAArgs& a, const 
   const int d2 = P.d / 2;
   switch (P.N2) {
 #define CS_CASE(L) case L: return launch_urow<L>(op, d2, grid, batch, a, st, s);
-    CS_CASE(16) CS_CASE(32) CS_CASE(64) CS_CASE(128) CS_CASE(256) CS_CASE(512) CS_CASE(1024)
+    CS_CASE(8) CS_CASE(16) CS_CASE(32) CS_CASE(64) CS_CASE(128) CS_CASE(256) CS_CASE(512) CS_CASE(1024)
     CS_CASE(2048) CS_CASE(4096) CS_CASE(8192)
 #undef CS_CASE
     default: return hipErrorInvalidValue;
@@ -614,7 +617,7 @@ hipError_t launchUB(const Plan& P, int mode, int batch, const PassBArgs& a, cons
   const int grid = P.N2 / kColsPerBlock;
   switch (P.N1) {
 #define CS_CASE(L) case L: return launch_ucol<L>(mode, grid, batch, a, st, s);
-    CS_CASE(8) CS_CASE(16) CS_CASE(32) CS_CASE(64) CS_CASE(128) CS_CASE(256) CS_CASE(512) CS_CASE(1024)
+    CS_CASE(4) CS_CASE(8) CS_CASE(16) CS_CASE(32) CS_CASE(64) CS_CASE(128) CS_CASE(256) CS_CASE(512) CS_CASE(1024)
     CS_CASE(2048)
 #undef CS_CASE
     default: return hipErrorInvalidValue;
@@ -1251,6 +1254,7 @@ cs_status cs_circ_apply_direct(const float* c, int64_t n, int32_t d, const float
   cs_status st = check_common(c, n, d);
   if (st != CS_OK) return st;
   if (d < 2) return fail(CS_EINVAL, "d=%d: the direct products take d in {2, 4, 8, 16}", d);
+  if (n < 256) return fail(CS_EINVAL, "n=%lld: the direct products take n >= 256", (long long)n);
   if (!x || !y) return fail(CS_EINVAL, "x or y is NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   CS_LAUNCH(timed(T_DIRECT, s, [&] { return launch_direct(0, d, c, x, y, n, s); }));
@@ -1263,6 +1267,7 @@ cs_status cs_circ_apply_T_direct(const float* c, int64_t n, int32_t d, const flo
   cs_status st = check_common(c, n, d);
   if (st != CS_OK) return st;
   if (d < 2) return fail(CS_EINVAL, "d=%d: the direct products take d in {2, 4, 8, 16}", d);
+  if (n < 256) return fail(CS_EINVAL, "n=%lld: the direct products take n >= 256", (long long)n);
   if (!r || !x) return fail(CS_EINVAL, "r or x is NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   CS_LAUNCH(timed(T_DIRECT_T, s, [&] { return launch_direct(1, d, c, r, x, n, s); }));
@@ -1359,8 +1364,8 @@ cs_status cs_cpadmm_solve(const float* c, int64_t n, const int64_t* omega_host, 
                           float alpha, float rho, float sigma, float tau, int32_t iters, float* x, float* v,
                           float* z, float* mu, float* nu, cs_stream stream) {
   if (!c || !y || !x || !v || !z || !mu || !nu) return fail(CS_EINVAL, "a device array is NULL");
-  if (!is_pow2(n) || n < kMinN || n > kCpMaxN)
-    return fail(CS_EINVAL, "n=%lld must be a power of two in [%lld, %lld]", (long long)n, (long long)kMinN,
+  if (!is_pow2(n) || n < kCpMinN || n > kCpMaxN)
+    return fail(CS_EINVAL, "n=%lld must be a power of two in [%lld, %lld]", (long long)n, (long long)kCpMinN,
                 (long long)kCpMaxN);
   if (m < 1 || m > n) return fail(CS_EINVAL, "m=%lld must be in [1, n]", (long long)m);
   if (!omega_host) return fail(CS_EINVAL, "omega is NULL");

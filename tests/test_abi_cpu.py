@@ -39,7 +39,7 @@ NULL = ctypes.c_void_p(0)
 FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every case below fails validation first
 
 
-@pytest.mark.parametrize("n,d", [(0, 4), (100, 4), (128, 4), (1 << 26, 4), (4096, 3), (4096, 6),
+@pytest.mark.parametrize("n,d", [(0, 4), (100, 4), (32, 4), (1 << 26, 4), (4096, 3), (4096, 6),
                                  (4096, 32), (4096, 0), (4096, -4)])
 def test_bad_sizes_rejected(n, d):
     lib = cs.load()

@@ -1,7 +1,9 @@
-"""GPU parity for d = 1 (A = C: every row kept, m = n), where every alias
-class is a single bin.  Operators, ISTA and ADMM iterates against the dense
-FP64 oracle (Alg. 1 and Alg. 2 with A = C written out) and at a larger size
-against the FFT oracle; the objective trace against the oracle's objective.
+"""GPU parity at the edges of the size range: d = 1 (A = C: every row kept,
+m = n), where every alias class is a single bin, and the smallest lengths
+n = 2^6, 2^7 for every d.  Operators, ISTA and ADMM iterates against the
+dense FP64 oracle (Alg. 1 and Alg. 2 with A written out) and at a larger
+size against the FFT oracle; the objective trace against the oracle's
+objective.
 Tolerances as in the other parity tests: relative l2 1e-4 per iterate,
 1e-5 per trace entry, operators to the FP32 transform error."""
 import numpy as np
@@ -123,3 +125,22 @@ def test_square_persistent_path_unsupported(square):
     finally:
         cs.set_solver_path(cs.PATH_AUTO)
     cs.check_device()
+
+
+@pytest.mark.parametrize("n,d", [(64, 1), (64, 2), (64, 4), (64, 16), (128, 1), (128, 4), (128, 8), (128, 16)])
+def test_smallest_sizes(n, d):
+    """n = 2^6 and 2^7 (8-point rows, 4-point columns): operators, ISTA and
+    ADMM iterates against the dense oracle."""
+    pr = problem.build(workloads.signal(n, d, 3, 31 * n + d))
+    A = pr.A()
+    x = pr.x_true.astype(np.float64)
+    assert rel(h(cs.circ_apply(g(pr.c), d, g(pr.x_true))), A @ x) <= 1e-5
+    r = pr.y.astype(np.float64)
+    assert rel(h(cs.circ_apply_T(g(pr.c), d, g(pr.y))), A.T @ r) <= 1e-5
+    _, hi = dense.ista(A, r, float(pr.lam), float(pr.tau), 50, record=True)
+    _, ha = dense.admm(A, r, float(pr.lam), 1.0, 50, record=True)
+    for t in (1, 5, 50):
+        assert rel(h(cs.ista_solve(g(pr.c), d, g(pr.y), pr.lam, pr.tau, t)), hi[t - 1]) <= IT_TOL, t
+        got = [h(v) for v in cs.admm_solve(g(pr.c), d, g(pr.y), pr.lam, 1.0, t)]
+        for name, a_, b_ in zip("xzu", got, ha[t - 1]):
+            assert rel(a_, b_) <= IT_TOL, (t, name)
