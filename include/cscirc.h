@@ -13,10 +13,10 @@
  *   - Every float pointer is a DEVICE pointer on the current HIP device,
  *     float32, densely packed, owned by the caller.  The library never frees
  *     or retains it beyond the work it enqueues.
- *   - n is a power of two with 64 <= n <= 2^25; d is 1, 2, 4, 8 or 16 with
- *     d <= n; m = n/d.  d = 1 (A = C, every row kept) and n < 256 run the
- *     two-launch schedule; the direct products take d >= 2 and n >= 256,
- *     the unrolled solver d >= 2.
+ *   - n is a power of two with 64 <= n <= 2^26; d is 1, 2, 4, 8 or 16 with
+ *     d <= n; m = n/d.  d = 1 (A = C, every row kept), n < 256 and n > 2^22
+ *     run the two-launch schedule; the direct products take d >= 2 and
+ *     n >= 256, the unrolled solver d >= 2 and n <= 2^25.
  *   - All work is enqueued on `stream` (a hipStream_t; 0 is the null stream)
  *     and the call returns without synchronising.  Outputs are valid once the
  *     stream has been synchronised.
@@ -89,7 +89,7 @@ cs_status cs_circ_norm_bound(const float* c, int64_t n, float* out, cs_stream st
  * each sum taken in double and rounded once to float.  Pass `out` as the
  * generator of any call above to solve with A = P C B.
  * c: n device floats, out: n device floats (distinct from c); n a power of
- * two in [2^6, 2^25] (the solvers' range); 1 <= L <= min(n, 4096) (O(n L)
+ * two in [2^6, 2^26] (the solvers' range); 1 <= L <= min(n, 4096) (O(n L)
  * work).  No allocation; CS_EINVAL on a bad argument, nothing enqueued.  */
 cs_status cs_box_blur_generator(const float* c, int64_t n, int32_t L, float* out, cs_stream stream);
 

@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcscirc.so")
 
 ROW_LENGTHS = [8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192]   # pass A (N2)
-COL_LENGTHS = [4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048]            # pass B (N1)
+COL_LENGTHS = [4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096]            # pass B (N1)
 SOLVE_LOGN = list(range(7, 22))                                     # persistent solver, N = 2^L
 BATCH_ALG = [0, 1]                                                  # persistent batched solver: ISTA, ADMM
 COL2_LENGTHS = [16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192]  # 2-D column pass (rows R)

@@ -31,6 +31,10 @@ hipError_t launch_ucol<CS_LEN>(int mode, int grid, int batch, const PassBArgs& a
                                hipStream_t s) {
   constexpr int L = CS_LEN;
   const dim3 g(grid, batch), b(kThreads);
+  if constexpr (L > 2048) {   // the unrolled solver takes n <= 2^25
+    (void)g; (void)b; (void)mode; (void)a; (void)st; (void)s;
+    return hipErrorInvalidValue;
+  } else {
   switch (mode) {
     case B_FWD_REAL: k_ucol<L, B_FWD_REAL><<<g, b, 0, s>>>(a, st); break;
     case B_FWD_UP: k_ucol<L, B_FWD_UP><<<g, b, 0, s>>>(a, st); break;
@@ -43,6 +47,7 @@ hipError_t launch_ucol<CS_LEN>(int mode, int grid, int batch, const PassBArgs& a
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+  }
 }
 
 template <>

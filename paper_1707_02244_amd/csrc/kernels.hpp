@@ -777,14 +777,23 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
   }
 }
 
-// Column-pass kernel: workgroup b owns columns [8b, 8b + 8).
+// Columns per column-pass workgroup of the two-launch schedule: 8 (64-byte
+// runs); 4 for 4096-point columns, whose 8-column block would not fit LDS.
+constexpr int pass_b_cols(int N1) { return N1 > 2048 ? 4 : kColsPerBlock; }
+
+// Column-pass kernel: workgroup b owns columns [CB b, CB b + CB).  The
+// stage twiddles are staged in LDS up to 2048-point columns and read from
+// the global table above.
 template <int N1, int MODE>
 __global__ __launch_bounds__(kThreads) void k_passB(PassBArgs a) {
-  __shared__ float2 lds[lds_padded(N1 * kColsPerBlock)];
-  __shared__ float2 tws[N1];
-  for (unsigned i = threadIdx.x; i < N1; i += kThreads) tws[i] = a.tw1[i];
+  constexpr int CB = pass_b_cols(N1);
+  constexpr bool TWL = N1 <= 2048;
+  __shared__ float2 lds[lds_padded(N1 * CB)];
+  __shared__ float2 tws_l[TWL ? N1 : 1];
+  if constexpr (TWL)
+    for (unsigned i = threadIdx.x; i < N1; i += kThreads) tws_l[i] = a.tw1[i];
   __syncthreads();
-  colpass<N1, MODE, kThreads>(a, blockIdx.x, lds, tws, threadIdx.x);
+  colpass<N1, MODE, kThreads, false, CB>(a, blockIdx.x, lds, TWL ? tws_l : a.tw1, threadIdx.x);
 }
 
 }  // namespace cs

@@ -185,7 +185,8 @@ using namespace rt;
 
 constexpr int64_t kMinN = 64;
 constexpr int64_t kCpMinN = 256;   // circulant ADMM with an arbitrary row set
-constexpr int64_t kMaxN = int64_t(1) << 25;
+constexpr int64_t kMaxN = int64_t(1) << 26;
+constexpr int64_t kMaxNUnrolled = int64_t(1) << 25;
 constexpr int64_t kCpMaxN = int64_t(1) << 22;   // circulant ADMM with an arbitrary row set
 constexpr int kMinLogNPersistent = 7;    // N = n/2 = 2^7 .. 2^21: one cooperative launch per solve
 constexpr int kMaxLogNPersistent = 21;
@@ -585,7 +586,7 @@ __global__ void k_box_blur(const float* __restrict__ c, int64_t n, int L, float*
 }
 
 hipError_t launchB(const Plan& P, int mode, const PassBArgs& a, hipStream_t s) {
-  const int grid = P.N2 / kColsPerBlock;
+  const int grid = P.N2 / pass_b_cols(P.N1);
   switch (P.N1) {
     case 4: return launch_passB<4>(mode, grid, a, s);
     case 8: return launch_passB<8>(mode, grid, a, s);
@@ -597,6 +598,7 @@ hipError_t launchB(const Plan& P, int mode, const PassBArgs& a, hipStream_t s) {
     case 512: return launch_passB<512>(mode, grid, a, s);
     case 1024: return launch_passB<1024>(mode, grid, a, s);
     case 2048: return launch_passB<2048>(mode, grid, a, s);
+    case 4096: return launch_passB<4096>(mode, grid, a, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -734,7 +736,7 @@ struct ObjBuf {
 ObjBuf g_obj[kMaxDevices];
 
 cs_status get_objbuf(const Plan& P, int iters, double** res, double** l1, hipStream_t s) {
-  const size_t nres = size_t(P.N1 / 2), nl1 = size_t(P.N2 / kColsPerBlock);
+  const size_t nres = size_t(P.N1 / 2), nl1 = size_t(P.N2 / pass_b_cols(P.N1));
   const size_t need = size_t(iters) * (nres + nl1);
   if (P.dev < 0 || P.dev >= kMaxDevices) return fail(CS_ENOTSUP, "device %d beyond the supported range", P.dev);
   std::lock_guard<std::mutex> lk(g_mu);
@@ -838,6 +840,7 @@ cs_status check_unrolled(const float* c, int64_t n, int d, int Bt, const float* 
   cs_status st = check_common(c, n, d);
   if (st != CS_OK) return st;
   if (d < 2) return fail(CS_EINVAL, "d=%d: the unrolled solver needs d >= 2", d);
+  if (n > kMaxNUnrolled) return fail(CS_EINVAL, "n=%lld: the unrolled solver takes n <= 2^25", (long long)n);
   if (!y || !lam || !tau) return fail(CS_EINVAL, "y, lam or tau is NULL");
   if (Bt < 1 || Bt > 65535) return fail(CS_EINVAL, "batch=%d must be in [1, 65535]", Bt);
   if (K < 1) return fail(CS_EINVAL, "K=%d must be >= 1", K);
@@ -899,7 +902,7 @@ cs_status ista_run(const Plan& V, const float* c, const float* y, float lambda, 
   if ((st = fill(x, size_t(n), 0.0f, s)) != CS_OK) return st;
   double *res = nullptr, *l1 = nullptr;
   if (obj && (st = get_objbuf(*P, iters, &res, &l1, s)) != CS_OK) return st;
-  const int nres = P->N1 / 2, nl1 = P->N2 / kColsPerBlock;
+  const int nres = P->N1 / 2, nl1 = P->N2 / pass_b_cols(P->N1);
   PassAArgs a = argsA(*P);
   a.tau = tau;
   PassBArgs b = argsB(*P);
@@ -1515,7 +1518,7 @@ cs_status cs_admm_solve(const float* c, int64_t n, int32_t d, const float* y, fl
   b.u = u;
   double *res = nullptr, *l1 = nullptr;
   if (obj && (st = get_objbuf(*P, iters, &res, &l1, s)) != CS_OK) return st;
-  const int nres = P->N1 / 2, nl1 = P->N2 / kColsPerBlock;
+  const int nres = P->N1 / 2, nl1 = P->N2 / pass_b_cols(P->N1);
   // objective trace: obj[t-1] = F(x(t)), both parts from iteration t
   for (int t = 1; t <= iters; ++t) {
     a.res = obj ? res + size_t(t - 1) * nres : nullptr;

@@ -39,7 +39,7 @@ NULL = ctypes.c_void_p(0)
 FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every case below fails validation first
 
 
-@pytest.mark.parametrize("n,d", [(0, 4), (100, 4), (32, 4), (1 << 26, 4), (4096, 3), (4096, 6),
+@pytest.mark.parametrize("n,d", [(0, 4), (100, 4), (32, 4), (1 << 27, 4), (4096, 3), (4096, 6),
                                  (4096, 32), (4096, 0), (4096, -4)])
 def test_bad_sizes_rejected(n, d):
     lib = cs.load()
@@ -150,7 +150,7 @@ def test_workspace_bytes_layout():
     y_hat tables, each part rounded up to 64 complex values."""
     lib = cs.load()
     up = lambda v: (v + 63) // 64 * 64
-    for n in (256, 4096, 1 << 17, 1 << 22):
+    for n in (64, 256, 4096, 1 << 17, 1 << 22, 1 << 26):
         N = n // 2
         L = N.bit_length() - 1
         N1 = 1 << ((L - 1) // 2) if L % 2 else 1 << (L // 2 - 1)
@@ -159,13 +159,13 @@ def test_workspace_bytes_layout():
         bar_words = 256 * 32 + 32
         parts = [up(bar_words // 2), 64, up(N1), up(N2), up(1 << lo), up(N >> lo), up(N1), up(N2),
                  up(N), up(N + 1), up(N + 1)]
-        for d in (2, 4, 8, 16):
+        for d in (1, 2, 4, 8, 16):
             for mode in (0, 1, 2):
                 assert lib.cs_workspace_bytes(n, d, mode) == 8 * sum(parts)
     assert lib.cs_workspace_bytes(1 << 22, 4, 3) == 0
     assert lib.cs_workspace_bytes(1000, 4, 1) == 0
     assert lib.cs_workspace_bytes(4096, 3, 1) == 0
-    assert lib.cs_workspace_bytes(1 << 26, 4, 1) == 0
+    assert lib.cs_workspace_bytes(1 << 27, 4, 1) == 0
 
 
 def test_bad_workspace_rejected():

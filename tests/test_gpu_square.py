@@ -144,3 +144,28 @@ def test_smallest_sizes(n, d):
         got = [h(v) for v in cs.admm_solve(g(pr.c), d, g(pr.y), pr.lam, 1.0, t)]
         for name, a_, b_ in zip("xzu", got, ha[t - 1]):
             assert rel(a_, b_) <= IT_TOL, (t, name)
+
+
+@pytest.mark.timeout(900)
+def test_largest_size():
+    """n = 2^26, d = 4 (4096-point columns in 4-column blocks): operators,
+    the first ISTA and ADMM iterates and their trace entries against the FFT
+    oracle."""
+    pr = problem.build(workloads.signal(1 << 26, 4, 1 << 16, 2026))
+    op = pr.op()
+    y = pr.y.astype(np.float64)
+    c, yg = g(pr.c), g(pr.y)
+    assert rel(h(cs.circ_apply(c, 4, g(pr.x_true))), op.A(pr.x_true.astype(np.float64))) <= 1e-5
+    assert rel(h(cs.circ_apply_T(c, 4, yg)), op.AT(y)) <= 1e-5
+    lam, tau = float(pr.lam), float(pr.tau)
+    _, hi = fftref.ista(op, y, lam, tau, 2, record=True)
+    obj = torch.empty(2, device=DEV)
+    x = h(cs.ista_solve(c, 4, yg, pr.lam, pr.tau, 2, obj=obj))
+    assert rel(x, hi[-1][1]) <= IT_TOL
+    ref = [fftref.objective(op, y, lam, v) for _, v in hi]
+    assert np.max(np.abs(h(obj) - ref) / ref) <= F_TOL
+    _, ha = fftref.admm(op, y, lam, 1.0, 2, record=True)
+    got = [h(v) for v in cs.admm_solve(c, 4, yg, pr.lam, 1.0, 2)]
+    for name, a_, b_ in zip("xzu", got, ha[-1][1:]):
+        assert rel(a_, b_) <= IT_TOL, name
+    cs.check_device()
