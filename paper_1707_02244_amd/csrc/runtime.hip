@@ -604,7 +604,7 @@ hipError_t launchB(const Plan& P, int mode, const PassBArgs& a, hipStream_t s) {
 }
 
 hipError_t launchUA(const Plan& P, int op, int batch, const PassAArgs& a, const UStride& st, hipStream_t s) {
-  const int grid = P.N1 / 2;
+  const int grid = P.N1 / 2 / urow_pairs(P.N2);
   const int d2 = P.d / 2;
   switch (P.N2) {
 #define CS_CASE(L) case L: return launch_urow<L>(op, d2, grid, batch, a, st, s);
@@ -616,7 +616,7 @@ hipError_t launchUA(const Plan& P, int op, int batch, const PassAArgs& a, const 
 }
 
 hipError_t launchUB(const Plan& P, int mode, int batch, const PassBArgs& a, const UStride& st, hipStream_t s) {
-  const int grid = P.N2 / kColsPerBlock;
+  const int grid = P.N2 / ucol_cols(P.N1);
   switch (P.N1) {
 #define CS_CASE(L) case L: return launch_ucol<L>(mode, grid, batch, a, st, s);
     CS_CASE(4) CS_CASE(8) CS_CASE(16) CS_CASE(32) CS_CASE(64) CS_CASE(128) CS_CASE(256) CS_CASE(512) CS_CASE(1024)
@@ -822,7 +822,7 @@ cs_status get_uplan(const Plan& P, int Bt, int every, int K, UPlan** out) {
     slot = std::move(u);
   }
   UPlan* u = slot.get();
-  const size_t need = size_t(K) * 2 * size_t(Bt) * size_t(P.N2 / kColsPerBlock);
+  const size_t need = size_t(K) * 2 * size_t(Bt) * size_t(P.N2 / ucol_cols(P.N1));
   if (u->part_cap < need) {
     if (u->part) (void)hipFree(u->part);
     u->part = nullptr;
@@ -960,7 +960,7 @@ cs_status cs_unrolled_ista_fwd(const float* c, int64_t n, int32_t d, int32_t Bt,
   // per-signal y_hat tables
   UStride us{};
   us.Y = N; us.yhat = N + 1; us.table = N + 1; us.in0 = m; us.u = n; us.out0 = m;
-  us.rv = n; us.rd = n; us.xbar = n; us.vbar = n; us.part = P->N2 / kColsPerBlock;
+  us.rv = n; us.rd = n; us.xbar = n; us.vbar = n; us.part = P->N2 / ucol_cols(P->N1);
   {
     PassBArgs b = argsB(*P);
     b.Y = U->Y;
@@ -1005,7 +1005,7 @@ cs_status cs_unrolled_ista_bwd(const float* c, int64_t n, int32_t d, int32_t Bt,
   UPlan* U = nullptr;
   if ((st = get_uplan(*P, Bt, every, K, &U)) != CS_OK) return st;
   const int64_t N = P->N, m = n / d;
-  const int nblk = P->N2 / kColsPerBlock;
+  const int nblk = P->N2 / ucol_cols(P->N1);
   const size_t BN = size_t(Bt) * size_t(n);
   if ((st = setup_chat(*P, c, s)) != CS_OK) return st;
   UStride us{};

@@ -1,8 +1,6 @@
 // Row and column passes over a batch of equal-length signals (grid y =
-// signal).  Used by the unrolled ISTA (signals sharing one sensing operator:
-// forward with per-iteration parameters and a checkpointed reverse pass) and
-// by the batched solver for groups of long signals of one length (each with
-// its own c_hat, tau and lambda).
+// signal), used by the unrolled ISTA (signals sharing one sensing operator:
+// forward with per-iteration parameters and a checkpointed reverse pass).
 //
 // The row and column passes of kernels.hpp run with a second grid dimension
 // over the signals of the batch; each signal has its own spectrum buffer,
@@ -36,11 +34,35 @@ struct UStride {
                     //   they are per iteration (indexed by t) instead
 };
 
+// Work per workgroup: about CS_U_ROW_PTS complex points per row item (AI
+// consecutive row pairs) and CS_U_COL_PTS per column item (CB adjacent
+// columns, at least 8), so that short signals do not run as many tiny
+// workgroups.  N1 >= N2 / 4 for every plan, so AI <= N2 / 8 divides N1 / 2.
+#ifndef CS_U_ROW_PTS
+#define CS_U_ROW_PTS 2048
+#endif
+#ifndef CS_U_COL_PTS
+#define CS_U_COL_PTS 2048
+#endif
+constexpr int urow_pairs(int N2) {
+  const int ai = CS_U_ROW_PTS / (2 * N2);
+  const int cap = N2 / 8 > 1 ? N2 / 8 : 1;
+  return ai < 1 ? 1 : (ai > cap ? cap : ai);
+}
+// capped at 2 N1, the smaller of the two N2 a plan can have, so that it
+// divides N2
+constexpr int ucol_cols(int N1) {
+  const int cb = CS_U_COL_PTS / N1;
+  const int w = cb > 2 * N1 ? 2 * N1 : cb;
+  return w < kColsPerBlock ? kColsPerBlock : w;
+}
+
 template <int N2, int OP, int D2>
 __global__ __launch_bounds__(kThreads) void k_urow(PassAArgs a, UStride st) {
+  constexpr int AI = urow_pairs(N2);
   constexpr int LD = N2 + kPadA;
-  constexpr bool TW_LDS = (lds_rows(2 * LD) + N2) * 8 <= 160 * 1024 - 1024;
-  __shared__ float2 lds[lds_rows(2 * LD)];
+  constexpr bool TW_LDS = (lds_rows(2 * AI * LD) + N2) * 8 <= 160 * 1024 - 1024;
+  __shared__ float2 lds[lds_rows(2 * AI * LD)];
   __shared__ float2 tws_l[TW_LDS ? N2 : 1];
   const long long b = blockIdx.y;
   a.Y += b * st.Y;
@@ -53,12 +75,13 @@ __global__ __launch_bounds__(kThreads) void k_urow(PassAArgs a, UStride st) {
     for (unsigned i = threadIdx.x; i < N2; i += kThreads) tws_l[i] = a.tw2[i];
   }
   __syncthreads();
-  rowpass<N2, OP, D2, kThreads>(a, blockIdx.x, lds, TW_LDS ? tws_l : a.tw2, threadIdx.x);
+  rowpass<N2, OP, D2, kThreads, false, AI>(a, blockIdx.x * AI, lds, TW_LDS ? tws_l : a.tw2, threadIdx.x);
 }
 
 template <int N1, int MODE>
 __global__ __launch_bounds__(kThreads) void k_ucol(PassBArgs a, UStride st) {
-  __shared__ float2 lds[lds_padded(N1 * kColsPerBlock)];
+  constexpr int CB = ucol_cols(N1);
+  __shared__ float2 lds[lds_padded(N1 * CB)];
   __shared__ float2 tws[N1];
   const long long b = blockIdx.y;
   a.Y += b * st.Y;
@@ -74,7 +97,7 @@ __global__ __launch_bounds__(kThreads) void k_ucol(PassBArgs a, UStride st) {
   if (a.lam_dev) a.lam_dev += b * st.par;
   for (unsigned i = threadIdx.x; i < N1; i += kThreads) tws[i] = a.tw1[i];
   __syncthreads();
-  colpass<N1, MODE, kThreads>(a, blockIdx.x, lds, tws, threadIdx.x);
+  colpass<N1, MODE, kThreads, false, CB>(a, blockIdx.x, lds, tws, threadIdx.x);
 }
 
 }  // namespace cs
