@@ -53,6 +53,9 @@ namespace cs {
 // us, with 16 VGPRs spilled)
 #define CS_COL2_MINW_LARGE 4
 #endif
+#ifndef CS_C2_LATE_G
+#define CS_C2_LATE_G 1   // column pass: class operands loaded after the forward transform
+#endif
 #ifndef CS_ROW2_MINW
 #define CS_ROW2_MINW 1   // row pass: same
 #endif
@@ -152,12 +155,16 @@ __global__ __launch_bounds__(col2_threads<R>(), col2_minw<R>()) void k2_col(Col2
     const unsigned i = tid + k * T;
     if (NE % T == 0 || i < NE) v[k] = a.T[(size_t)w * NE + i];   // element (r = i/2, slot i%2)
   }
-  // group operands: g_hat at the class's four bins, Y_hat of the class
+  // group operands: g_hat at the class's four bins, Y_hat of the class.
+  // Loaded with the column (early) or after the forward transform (late:
+  // they are then not live across it, which keeps the R = 4096 pass within
+  // 128 VGPRs without spills)
   constexpr int NGMAX = HR;   // groups per workgroup (w > 0); workgroup 0 has R/2 + 2
   constexpr int GPT = GROUP ? (NGMAX + 2 + T - 1) / T : 1;
+  constexpr bool LATE_G = CS_C2_LATE_G && GPT > 2;
   const int ng = w ? HR : 2 * (R / 4 + 1);
   float2 gg[GPT][4], gy[GPT];
-  if constexpr (GROUP) {
+  auto load_groups = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int k = 0; k < GPT; ++k) {
       const int g = tid + k * T;
@@ -173,7 +180,8 @@ __global__ __launch_bounds__(col2_threads<R>(), col2_minw<R>()) void k2_col(Col2
         gy[k] = a.Yt[(size_t)p * HR + k1];
       }
     }
-  }
+  };
+  if constexpr (GROUP && !LATE_G) load_groups();
   if constexpr (TW_LDS) {
     for (unsigned i = tid; i < R; i += T) tws_l[i] = a.twR[i];
   }
@@ -187,6 +195,7 @@ __global__ __launch_bounds__(col2_threads<R>(), col2_minw<R>()) void k2_col(Col2
 
   float res_acc = 0.0f;
   if constexpr (GROUP) {
+    if constexpr (LATE_G) load_groups();
 #pragma unroll
     for (int k = 0; k < GPT; ++k) {
       const int g = tid + k * T;
