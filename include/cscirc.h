@@ -289,10 +289,14 @@ cs_status cs_set_workspace(void* ws, size_t bytes);
  * n, alpha >= 0, rho > 0, sigma > 0, tau > 0 (the section quotes tau <
  * (1 + sqrt 5)/2 for convergence), iters >= 0; CS_EINVAL otherwise,
  * including a repeated or out-of-range index in omega.  Uses the (n, d = 2)
- * plan of the single-signal calls (its two spectrum buffers and c_hat
- * table).  During the solve v holds P^T y and z the indicator of omega, and
- * omega's indices are copied through x: the call synchronises the stream
- * once, after that copy.  Two launches per iteration.  */
+ * plan of the single-signal calls for its c_hat table and twiddles, and a
+ * working buffer of the library (24 n bytes: both signals' spectra and the
+ * column-blocked mu, nu, P^T y and indicator of omega), allocated with
+ * hipMalloc on the first call of a larger n on a device and kept until the
+ * process ends; calls on one device share it (serialise them).  omega's
+ * indices are copied through x: the call synchronises the stream once, after
+ * that copy.  The last iteration writes x, v, z, mu and nu.  Two launches
+ * per iteration.  */
 cs_status cs_cpadmm_solve(const float* c, int64_t n, const int64_t* omega_host, int64_t m, const float* y,
                           float alpha, float rho, float sigma, float tau, int32_t iters, float* x, float* v,
                           float* z, float* mu, float* nu, cs_stream stream);
