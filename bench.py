@@ -185,6 +185,24 @@ def main():
         "admm_ms_per_solve": admm_ms,
     }
 
+    # the same two solves with an objective trace (one launch each as well),
+    # outside the timed steps
+    progress("headline: traced solves")
+    obj = torch.empty(T_ista, device=dev)
+    cs.ista_solve(c, d, y, lam, tau, T_ista, x=x, obj=obj)
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    cs.ista_solve(c, d, y, lam, tau, T_ista, x=x, obj=obj)
+    e1.record()
+    cs.admm_solve(c, d, y, lam, rho, T_admm, x=xa, z=za, u=ua, obj=obj[:T_admm])
+    e2.record()
+    torch.cuda.synchronize()
+    out["traced"] = {"ista_it_s": T_ista / (e0.elapsed_time(e1) / 1e3),
+                     "admm_it_s": T_admm / (e1.elapsed_time(e2) / 1e3),
+                     "note": "cs_ista_solve / cs_admm_solve with obj != NULL (per-iteration objective "
+                             "trace inside the single-launch solve); not part of value"}
+
     kb = kernel_bytes(n, d, T_ista, T_admm)
 
     if not args.no_roofline:
