@@ -230,6 +230,14 @@ def main():
                                            "Cache, which holds this solve's ~100 MB working set, and no gfx950 "
                                            "counter separates the two"}
         out["kernels"] = kern
+        # per solve call: the solve kernel and what runs around it (the c_hat
+        # and y_hat set-up transforms, the barrier reset, launch gaps); the
+        # headline value counts both
+        out["solve_split_ms"] = {
+            alg: {"call": call_ms, "solve_kernel": kern[k]["avg_us"] / 1e3,
+                  "setup_and_gaps": call_ms - kern[k]["avg_us"] / 1e3}
+            for alg, call_ms, k in (("ista", ista_ms, "solve_ista"), ("admm", admm_ms, "solve_admm"))
+            if k in kern}
         out["bytes_model"] = ITER_BYTES_NOTE
         cs.check_device()
         # context for the roofline: the compulsory-bytes rate (state in and
