@@ -58,6 +58,35 @@ def test_unrolled_rejects_square_operator():
     assert b"d >= 2" in lib.cs_last_error()
 
 
+def test_unrolled_rejects_largest_size():
+    """n = 2^26 is a valid operator and solver size; the unrolled solver
+    takes n <= 2^25."""
+    lib = cs.load()
+    assert lib.cs_unrolled_ista_fwd(FAKE, 1 << 26, 4, 2, FAKE, FAKE, FAKE, 5, 0, FAKE, NULL, NULL) == _lib.CS_EINVAL
+    assert b"2^25" in lib.cs_last_error()
+
+
+@pytest.mark.parametrize("n,L,same", [(4096, 0, False), (4096, -3, False), (256, 257, False), (1 << 14, 4097, False),
+                                      (4096, 5, True), (1000, 5, False), (32, 5, False)])
+def test_box_blur_generator_bad_arguments(n, L, same):
+    """The C B generator validates n, the order L and aliasing on the host,
+    before anything is enqueued."""
+    lib = cs.load()
+    out = FAKE if same else ctypes.c_void_p(0x2000)
+    assert lib.cs_box_blur_generator(FAKE, n, L, out, NULL) == _lib.CS_EINVAL
+    assert lib.cs_last_error()
+    assert lib.cs_box_blur_generator(NULL, 4096, 5, out, NULL) == _lib.CS_EINVAL
+    assert lib.cs_box_blur_generator(FAKE, 4096, 5, NULL, NULL) == _lib.CS_EINVAL
+
+
+def test_direct_products_reject_small_n():
+    """n = 2^6 and 2^7 are valid for the FFT operators but not for the direct
+    products (n >= 2^8)."""
+    lib = cs.load()
+    assert lib.cs_circ_apply_direct(FAKE, 128, 4, FAKE, FAKE, NULL) == _lib.CS_EINVAL
+    assert b"n >= 256" in lib.cs_last_error()
+
+
 def test_null_pointers_rejected():
     lib = cs.load()
     assert lib.cs_circ_apply(NULL, 4096, 4, FAKE, FAKE, NULL) == _lib.CS_EINVAL
@@ -229,6 +258,7 @@ def test_batched_null_and_count_checks():
 @pytest.mark.parametrize("n,omega,alpha,rho,sigma,tau,iters", [
     (1000, [0, 1], 0.1, 1.0, 1.0, 1.0, 5),           # n not a power of two
     (1 << 23, [0, 1], 0.1, 1.0, 1.0, 1.0, 5),        # n above 2^22
+    (128, [0, 1], 0.1, 1.0, 1.0, 1.0, 5),            # n below 2^8 (this call's minimum)
     (4096, [0, 4096], 0.1, 1.0, 1.0, 1.0, 5),        # index out of range
     (4096, [-1, 3], 0.1, 1.0, 1.0, 1.0, 5),
     (4096, [7, 3, 7], 0.1, 1.0, 1.0, 1.0, 5),        # repeated index
