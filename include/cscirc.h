@@ -317,13 +317,14 @@ cs_status cs_cpadmm_solve(const float* c, int64_t n, const int64_t* omega_host, 
 cs_status cs_ista_solve_noalloc(const float* c, int64_t n, int32_t d, const float* y, float lambda, float tau,
                                 int32_t iters, float* x, cs_stream stream);
 
-/* Solver schedule.  For 2^8 <= n <= 2^22 a solve runs as ONE cooperative
- * launch: all iterations in a persistent kernel whose workgroups keep the
- * time-domain state in registers and meet at a grid barrier between the row
- * and column passes.  Larger n (or path 1) uses two launches per iteration
- * with the state in HBM.  Both compute the same iterates.  path: 0 = choose
- * per size (default), 1 = two launches per iteration, 2 = persistent (the
- * solve returns CS_ENOTSUP where it does not fit).  Process-wide.  */
+/* Solver schedule.  For 2^8 <= n <= 2^22 and d >= 2 a solve runs as ONE
+ * cooperative launch, with or without an objective trace: all iterations in
+ * a persistent kernel whose workgroups keep the time-domain state in
+ * registers and meet at a grid barrier between the row and column passes.
+ * Other sizes, d = 1 (or path 1) use two launches per iteration with the
+ * state in HBM.  Both compute the same iterates.  path: 0 = choose per size
+ * (default), 1 = two launches per iteration, 2 = persistent (the solve
+ * returns CS_ENOTSUP where it does not apply).  Process-wide.  */
 cs_status cs_set_solver_path(int32_t path);
 
 /* Synchronise `stream` and report device-side errors of earlier solves on
