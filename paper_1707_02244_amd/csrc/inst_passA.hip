@@ -12,7 +12,7 @@ namespace cs {
 template <>
 hipError_t launch_passA<CS_LEN>(int op, int d2, int grid, const PassAArgs& a, hipStream_t s) {
   constexpr int L = CS_LEN;
-  const dim3 g(grid), b(kThreads);
+  const dim3 g(grid), b(pass_a_threads(L));
 #define CS_GROUP_OP(OPV)                                                              \
   switch (d2) {                                                                       \
     case 0: k_passA<L, OPV, 0><<<g, b, 0, s>>>(a); break;                             \

@@ -12,7 +12,7 @@ namespace cs {
 template <>
 hipError_t launch_passB<CS_LEN>(int mode, int grid, const PassBArgs& a, hipStream_t s) {
   constexpr int L = CS_LEN;
-  const dim3 g(grid), b(kThreads);
+  const dim3 g(grid), b(pass_b_threads(L));
   switch (mode) {
     case B_FWD_REAL: k_passB<L, B_FWD_REAL><<<g, b, 0, s>>>(a); break;
     case B_FWD_UP: k_passB<L, B_FWD_UP><<<g, b, 0, s>>>(a); break;

@@ -49,6 +49,15 @@
 namespace cs {
 
 constexpr int kThreads = 256;
+// Threads of the two-launch row and column passes: 256, more for the long
+// rows and columns of n >= 2^23 (2 x 4096-point rows, 1024- to 4096-point
+// columns in blocks of 8 or 4), whose single workgroup per CU would
+// otherwise hold 4 waves.
+#ifndef CS_PASS_WIDE
+#define CS_PASS_WIDE 1
+#endif
+constexpr int pass_a_threads(int N2) { return CS_PASS_WIDE && N2 >= 8192 ? 1024 : (CS_PASS_WIDE && N2 >= 4096 ? 512 : kThreads); }
+constexpr int pass_b_threads(int N1) { return CS_PASS_WIDE && N1 >= 2048 ? 1024 : (CS_PASS_WIDE && N1 >= 1024 ? 512 : kThreads); }
 constexpr int kColsPerBlock = 8;   // pass B: adjacent columns per workgroup (64 B runs)
 constexpr int kPadA = CS_ROW_PAD ? 0 : 4;   // pass A: float2 padding between rows
 
@@ -213,8 +222,10 @@ __device__ __forceinline__ float2 tw_N(const PassBArgs& a, int e) {
 // that are their own mirror images, {0, N1/2}.  Rows are held in LDS slots 0
 // and 1.  D2 = d/2 bins per alias-class side; D2 = 0 stands for d = 1
 // (m = n): every bin is its own class, and A_ISTA, A_ADMM and A_RES run on
-// the split pairs (k, N - k) with y_hat read at both bins.
-template <int N2, int OP, int D2, int T, bool COH = false, int AI = 1>
+// the split pairs (k, N - k) with y_hat read at both bins.  LATE: load the
+// class operands after the forward row transforms instead of with the rows
+// (fewer registers live across the transforms).
+template <int N2, int OP, int D2, int T, bool COH = false, int AI = 1, bool LATE = false>
 __device__ __forceinline__ void rowpass(const PassAArgs& a, int w0, float2* __restrict__ lds,
                                         const float2* __restrict__ tws, unsigned tid) {
   constexpr int LD = N2 + kPadA;
@@ -261,7 +272,7 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w0, float2* __re
   float2 gca[GPT][DA], gcb[GPT][DA], gw[GPT][DA], gy[GPT];
   const int M = MC;
   const int ng = (w0 ? M : (M + 1)) + (AI - 1) * M;   // classes of the held pairs
-  if constexpr (GROUP) {
+  auto load_classes = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int k = 0; k < GPT; ++k) {
       const int gi = tid + k * T;
@@ -289,7 +300,8 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w0, float2* __re
         else if constexpr (OP == A_TILE) gy[k] = a.ybar[(size_t)rowa * N2 + k2];
       }
     }
-  }
+  };
+  if constexpr (GROUP && !LATE) load_classes();
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const int i = tid + k * T;
@@ -297,6 +309,7 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w0, float2* __re
   }
   __syncthreads();
   lds_fft<N2, 2 * AI, T, false, false, LD>(lds, tws, tid);
+  if constexpr (GROUP && LATE) load_classes();
 
   // objective trace: this thread's sum of weight * |Y_hat - S|^2; a class
   // stands for m-point bins k' and m - k' (weight 2) unless k' is 0 or m/2
@@ -516,16 +529,20 @@ __device__ __forceinline__ void rowpass(const PassAArgs& a, int w0, float2* __re
 // twiddles W_{N2}^e are copied to LDS when both rows and the table fit in the
 // 160 KiB of a CU, and read from the global table otherwise.
 template <int N2, int OP, int D2>
-__global__ __launch_bounds__(kThreads) void k_passA(PassAArgs a) {
+__global__ __launch_bounds__(pass_a_threads(N2)) void k_passA(PassAArgs a) {
+  constexpr int TA = pass_a_threads(N2);
   constexpr int LD = N2 + kPadA;
   constexpr bool TW_LDS = (lds_rows(2 * LD) + N2) * 8 <= 160 * 1024 - 1024;
   __shared__ float2 lds[lds_rows(2 * LD)];
   __shared__ float2 tws_l[TW_LDS ? N2 : 1];
   if constexpr (TW_LDS) {
-    for (unsigned i = threadIdx.x; i < N2; i += kThreads) tws_l[i] = a.tw2[i];
+    for (unsigned i = threadIdx.x; i < N2; i += TA) tws_l[i] = a.tw2[i];
   }
   __syncthreads();
-  rowpass<N2, OP, D2, kThreads>(a, blockIdx.x, lds, TW_LDS ? tws_l : a.tw2, threadIdx.x);
+  // long rows: class operands loaded after the forward transforms (three or
+  // more classes per thread would otherwise be held across them)
+  constexpr bool LATE = (N2 / (D2 > 0 ? D2 : 1) + 1 + TA - 1) / TA >= 3;
+  rowpass<N2, OP, D2, TA, false, 1, LATE>(a, blockIdx.x, lds, TW_LDS ? tws_l : a.tw2, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -777,6 +794,7 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
   }
 }
 
+
 // Columns per column-pass workgroup of the two-launch schedule: 8 (64-byte
 // runs); 4 for 4096-point columns, whose 8-column block would not fit LDS.
 constexpr int pass_b_cols(int N1) { return N1 > 2048 ? 4 : kColsPerBlock; }
@@ -785,15 +803,16 @@ constexpr int pass_b_cols(int N1) { return N1 > 2048 ? 4 : kColsPerBlock; }
 // stage twiddles are staged in LDS up to 2048-point columns and read from
 // the global table above.
 template <int N1, int MODE>
-__global__ __launch_bounds__(kThreads) void k_passB(PassBArgs a) {
+__global__ __launch_bounds__(pass_b_threads(N1)) void k_passB(PassBArgs a) {
+  constexpr int TB = pass_b_threads(N1);
   constexpr int CB = pass_b_cols(N1);
   constexpr bool TWL = N1 <= 2048;
   __shared__ float2 lds[lds_padded(N1 * CB)];
   __shared__ float2 tws_l[TWL ? N1 : 1];
   if constexpr (TWL)
-    for (unsigned i = threadIdx.x; i < N1; i += kThreads) tws_l[i] = a.tw1[i];
+    for (unsigned i = threadIdx.x; i < N1; i += TB) tws_l[i] = a.tw1[i];
   __syncthreads();
-  colpass<N1, MODE, kThreads, false, CB>(a, blockIdx.x, lds, TWL ? tws_l : a.tw1, threadIdx.x);
+  colpass<N1, MODE, TB, false, CB>(a, blockIdx.x, lds, TWL ? tws_l : a.tw1, threadIdx.x);
 }
 
 }  // namespace cs
