@@ -799,9 +799,24 @@ __device__ __forceinline__ void colpass(const PassBArgs& a, int blk, float2* __r
 // runs); 4 for 4096-point columns, whose 8-column block would not fit LDS.
 constexpr int pass_b_cols(int N1) { return N1 > 2048 ? 4 : kColsPerBlock; }
 
-// Column-pass kernel: workgroup b owns columns [CB b, CB b + CB).  The
-// stage twiddles are staged in LDS up to 2048-point columns and read from
-// the global table above.
+#ifndef CS_PASSB_XCD
+#define CS_PASSB_XCD 1
+#endif
+
+// Column block of the column pass's workgroup b.  Workgroups are dispatched
+// round-robin over the 8 XCDs, each with its own L2; a column block's rows are
+// CB * 8 bytes, less than a 128-byte line, so neighbouring blocks share lines.
+// XCD x takes the contiguous range [x G/8, (x + 1) G/8) in order, so the
+// workgroups resident on one XCD at a time read and write whole lines through
+// the same L2 (a permutation of the blocks whenever G is a multiple of 8).
+__device__ __forceinline__ int passb_block(unsigned b, unsigned G) {
+  if (CS_PASSB_XCD && (G & 7u) == 0) return (int)((b & 7u) * (G >> 3) + (b >> 3));
+  return (int)b;
+}
+
+// Column-pass kernel: the workgroup owns columns [CB blk, CB blk + CB), blk
+// as above.  The stage twiddles are staged in LDS up to 2048-point columns
+// and read from the global table above.
 template <int N1, int MODE>
 __global__ __launch_bounds__(pass_b_threads(N1)) void k_passB(PassBArgs a) {
   constexpr int TB = pass_b_threads(N1);
@@ -812,7 +827,7 @@ __global__ __launch_bounds__(pass_b_threads(N1)) void k_passB(PassBArgs a) {
   if constexpr (TWL)
     for (unsigned i = threadIdx.x; i < N1; i += TB) tws_l[i] = a.tw1[i];
   __syncthreads();
-  colpass<N1, MODE, TB, false, CB>(a, blockIdx.x, lds, TWL ? tws_l : a.tw1, threadIdx.x);
+  colpass<N1, MODE, TB, false, CB>(a, passb_block(blockIdx.x, gridDim.x), lds, TWL ? tws_l : a.tw1, threadIdx.x);
 }
 
 }  // namespace cs
