@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--no-deblur1d", action="store_true")
     ap.add_argument("--no-cpadmm", action="store_true")
     ap.add_argument("--no-recovery", action="store_true")
+    ap.add_argument("--large-n", action="store_true",
+                    help="also time ISTA at n = 2^23 .. 2^26 (d = 4, two-launch schedule)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain copy kernel (read and write this many MiB, 3 launches): the "
                          "known-size reference that scales profiler byte counters")
@@ -272,6 +274,8 @@ def main():
     if not args.no_cpadmm:
         progress("circulant ADMM, random rows: n=2^22, m=n/2")
         out["cpadmm_random_rows"] = bench_cpadmm(cs, torch, dev, args.steps, args.warmup)
+    if args.large_n:
+        out["large_n"] = bench_large_n(cs, torch, dev)
     if not args.no_recovery:
         progress("recovery time to MSE 1e-4 at n=2^15")
         out["recovery"] = bench_recovery(cs, torch, dev)
@@ -365,6 +369,45 @@ def bench_batched(cs, torch, dev, steps, warmup):
 
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X fp32 vector peak (counts packed FP32; these kernels are built without it)
+
+
+def bench_large_n(cs, torch, dev, iters=100):
+    """Sizes above the persistent solver's range: ISTA at n = 2^23 .. 2^26,
+    d = 4, k = n/256, lambda = 1e-2, on the two-launch schedule (one row and
+    one column launch per iteration).  Per size: microseconds per iteration
+    of the whole call and of each pass (HIP events around every launch), and
+    the column pass's rate on the 16n bytes it must move (spectrum and
+    time-domain state, each read and written once)."""
+    import workloads
+    res = {}
+    for logn in (23, 24, 25, 26):
+        n = 1 << logn
+        progress("large n: 2^%d" % logn)
+        sig = workloads.signal(n, 4, n // 256, 1000 + logn)
+        c = torch.from_numpy(sig.c).to(dev)
+        y = cs.circ_apply(c, 4, torch.from_numpy(sig.x_true).to(dev))
+        tau = 1.0 / float(cs.circ_norm_bound(c).item())
+        x = torch.empty_like(c)
+        cs.ista_solve(c, 4, y, 0.01, tau, iters, x=x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cs.ista_solve(c, 4, y, 0.01, tau, iters, x=x)
+        e1.record()
+        torch.cuda.synchronize()
+        call_us = e0.elapsed_time(e1) * 1e3 / iters
+        cs.timing_enable(True)
+        cs.ista_solve(c, 4, y, 0.01, tau, iters, x=x)
+        torch.cuda.synchronize()
+        cs.timing_enable(False)
+        (ca, ta), (cb, tb) = cs.timing_read("passA_ista"), cs.timing_read("passB_ista")
+        cs.check_device()
+        row_us, col_us = ta * 1e3 / max(1, ca), tb * 1e3 / max(1, cb)
+        res["2^%d" % logn] = {"us_per_it": call_us, "row_us": row_us, "col_us": col_us,
+                              "col_GBs_on_16n": 16 * n / (col_us * 1e3)}
+        del c, y, x
+    res["workload"] = "ISTA d=4, k=n/256, lambda=1e-2, %d iterations per call" % iters
+    return res
 
 
 def bench_direct(cs, torch, dev, c, d, xs, y):
