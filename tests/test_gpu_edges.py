@@ -31,16 +31,19 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
 
-def test_largest_n_operator_and_first_iterates():
-    """n = 2^25 (m = 2^23, d = 4): beyond the persistent solver's range, so
-    the two-launch schedule runs; operators and the first ISTA / ADMM
-    iterates against the FFT oracle."""
-    n, d = 1 << 25, 4
-    rng = np.random.default_rng(25)
+@pytest.mark.parametrize("n,d", [(1 << 25, 4), (1 << 24, 2), (1 << 24, 16), (1 << 23, 4)])
+def test_largest_n_operator_and_first_iterates(n, d):
+    """n = 2^23 .. 2^25: beyond the persistent solver's range, so the
+    two-launch schedule runs (4096-point rows at 2^23 and 2^24 with 512
+    threads, 8192-point rows and 2048-point columns with 1024 at 2^25; d = 2
+    and 4 hold three or more classes per row-pass thread, d = 16 fewer);
+    operators and the first ISTA / ADMM iterates against the FFT oracle."""
+    rng = np.random.default_rng(n.bit_length() * 100 + d)
     m = n // d
     c = (rng.standard_normal(n) / np.sqrt(m)).astype(np.float32)
     x = np.zeros(n, np.float32)
-    x[rng.choice(n, 1 << 15, replace=False)] = rng.standard_normal(1 << 15)
+    k = n >> 10
+    x[rng.choice(n, k, replace=False)] = rng.standard_normal(k)
     op = fftref.Operator(c.astype(np.float64), d)
     yref = op.A(x.astype(np.float64))
     cg = g(c)
